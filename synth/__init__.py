@@ -1,0 +1,114 @@
+"""Seeded synthetic inputs for the C-A / CUR workloads.
+
+Shared by the tests, the smoke check and the benchmark.  This module holds no
+arithmetic of the method itself: it only draws matrices, point sets, index
+sets and request streams with numpy's PCG64 ``default_rng(seed)``, in a fixed
+draw order, so that the CPU oracle and the GPU library see identical bits.
+
+Workload recipes (the paper's own benchmark matrices -- the San Jose State
+singular-matrix collection, the Toeplitz-derived Cauchy-like matrices of its
+HSS tests, the finite-difference operator -- are not available, so these
+seeded inputs stand in for them):
+
+* ``plain_fp64`` -- W = G1 G2 + eps G3 with Gaussian factors, the perturbed
+  factor-Gaussian family of Section 12.3 (the paper uses eps = 1e-10; the
+  512 x 512, rank-8 workload here uses eps = 1e-8).
+* ``dense_scaled`` -- A = G1 G2 D + noise, D log-uniform column scales in
+  [0.1, 10], noise N(0,1) scaled to 1e-4 of ||G1 G2 D||_F, stored float32.
+* ``cauchy_points`` -- s ~ U[0,1], t ~ U[2,3]: a_ij = 1/(s_i - t_j), the
+  Cauchy-like kernel of the HSS experiments (Section 12.8).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Draws:
+    """Index sets that the method consumes as random input."""
+    cand_cols: np.ndarray   # J0 = cand_cols[:k]; rank growth takes the rest in order
+    sample_rows: np.ndarray  # residual sample Q (sorted, distinct)
+    sample_cols: np.ndarray  # residual sample S (sorted, distinct)
+
+
+def residual_sample(m: int, n: int, seed: int, q: int = 64, s: int = 64):
+    """Q, S for the a posteriori estimate: a fresh default_rng(seed + 1)."""
+    rng = np.random.default_rng(seed + 1)
+    q = min(q, m)
+    s = min(s, n)
+    Q = np.sort(rng.choice(m, q, replace=False)).astype(np.int64)
+    S = np.sort(rng.choice(n, s, replace=False)).astype(np.int64)
+    return Q, S
+
+
+def plain_fp64(seed: int = 0, n: int = 512, r: int = 8, eps: float = 1e-8, k: int | None = None):
+    """Perturbed factor-Gaussian W = G1 G2 + eps E (float64, row-major).
+
+    Draw order: G1 (n x r), G2 (r x n), E (n x n), then J0 = choice(n, k)."""
+    k = r if k is None else k
+    rng = np.random.default_rng(seed)
+    G1 = rng.standard_normal((n, r))
+    G2 = rng.standard_normal((r, n))
+    E = rng.standard_normal((n, n))
+    A = G1 @ G2 + eps * E
+    J0 = rng.choice(n, k, replace=False).astype(np.int64)
+    Q, S = residual_sample(n, n, seed)
+    return A, Draws(J0, Q, S)
+
+
+def rect_factor_gaussian(seed: int, m: int, n: int, r: int, eps: float, k: int,
+                         dtype=np.float64, n_cand: int | None = None):
+    """Rectangular perturbed factor-Gaussian matrix, for parity sweeps."""
+    rng = np.random.default_rng(seed)
+    G1 = rng.standard_normal((m, r))
+    G2 = rng.standard_normal((r, n))
+    E = rng.standard_normal((m, n))
+    A = (G1 @ G2 + eps * E).astype(dtype)
+    cand = rng.choice(n, n_cand or k, replace=False).astype(np.int64)
+    Q, S = residual_sample(m, n, seed)
+    return A, Draws(cand, Q, S)
+
+
+def dense_scaled(seed: int = 0, n: int = 16384, r: int = 32, k: int = 32, rel_noise: float = 1e-4,
+                 chunk: int = 2048):
+    """A = G1 G2 D + rel_noise (||G1 G2 D||_F / ||E||_F) E, cast to float32.
+
+    Draw order: G1 (n x r), G2 (r x n), the log-uniform column scales d
+    (U[ln 0.1, ln 10], exponentiated), E (n x n, row-major), J0 = choice(n, k).
+    Row chunks of E are drawn in sequence, which reproduces one n x n draw."""
+    rng = np.random.default_rng(seed)
+    G1 = rng.standard_normal((n, r))
+    G2 = rng.standard_normal((r, n))
+    d = np.exp(rng.uniform(np.log(0.1), np.log(10.0), n))
+    G2d = G2 * d[None, :]
+    # ||G1 G2 D||_F^2 = sum_j (G2d[:, j]^T (G1^T G1) G2d[:, j])
+    M = G1.T @ G1
+    norm_l = float(np.sqrt(np.einsum("ij,ik,kj->", G2d, M, G2d)))
+    E = np.empty((n, n), dtype=np.float64)
+    for r0 in range(0, n, chunk):
+        E[r0:r0 + chunk] = rng.standard_normal((min(chunk, n - r0), n))
+    norm_e = float(np.sqrt(np.einsum("ij,ij->", E, E)))
+    c = rel_noise * norm_l / norm_e
+    A = np.empty((n, n), dtype=np.float32)
+    for r0 in range(0, n, chunk):
+        r1 = min(n, r0 + chunk)
+        A[r0:r1] = (G1[r0:r1] @ G2d + c * E[r0:r1]).astype(np.float32)
+    del E
+    J0 = rng.choice(n, k, replace=False).astype(np.int64)
+    Q, S = residual_sample(n, n, seed)
+    return A, Draws(J0, Q, S)
+
+
+def cauchy_points(seed: int = 0, m: int = 1 << 20, n: int | None = None, k: int = 8,
+                  k_max: int = 40, dtype=np.float64):
+    """s ~ U[0,1]^m, t ~ U[2,3]^n (drawn in that order), then the candidate
+    column list choice(n, min(n, 2 k_max)) whose first k entries are J0."""
+    n = m if n is None else n
+    rng = np.random.default_rng(seed)
+    s = rng.uniform(0.0, 1.0, m)
+    t = rng.uniform(2.0, 3.0, n)
+    cand = rng.choice(n, min(n, 2 * max(k, k_max)), replace=False).astype(np.int64)
+    Q, S = residual_sample(m, n, seed)
+    return s.astype(dtype), t.astype(dtype), Draws(cand, Q, S)
