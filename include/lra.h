@@ -1,0 +1,209 @@
+/*
+ * lra.h -- C ABI of the MI355X (gfx950) Cross-Approximation / CUR library.
+ *
+ * The method (Pan, Luan, Svadlenka, Zhao, "Superfast Low-Rank Approximation
+ * and Least Squares Regression", arXiv:1611.01391):
+ *   - the LRA problem: an m x n matrix M and a target rank (Section 5.1);
+ *   - CUR LRA from a row set I and a column set J, generator M_{I,J} and
+ *     nucleus U (Section 6.5, "Primitive, Cynical, and Cross-Approximation
+ *     Algorithms and CUR LRA"); U = M_{I,J}^{-1} for k = l = r as in the C-A
+ *     experiments (Section 12.2, eq. (eqtsts1));
+ *   - C-A iterations alternating vertical and horizontal steps, here in the
+ *     dual order that starts with a vertical (column) step (Remark
+ *     rec-atnsr); each step picks a k x k submatrix of locally maximal volume
+ *     in the strip (Section 6.5, footnote defining the volume; Remark
+ *     "re vlmmx" for the cost model);
+ *   - FAILURE when the sketch is rank deficient, and the remedy of raising
+ *     the rank (Algorithm 5.1, its footnotes);
+ *   - a posteriori estimation on a random q x s submatrix of the error
+ *     matrix (Appendix F).
+ *
+ * Conventions for every entry point:
+ *   - indices are 0-based int64;
+ *   - "device" pointers are HIP device memory on the context's device (a
+ *     PyTorch CUDA/HIP tensor's data_ptr() qualifies); "host" pointers are
+ *     ordinary host memory;
+ *   - all device work is enqueued on the context's stream; the blocking
+ *     calls (lra_ca_cur, lra_ca_cur_batched, lra_maxvol, lra_wait) return
+ *     after the results are on the host;
+ *   - input matrices / point sets are owned by the caller and must stay valid
+ *     and unmodified until the call returns (or the ticket completes);
+ *   - outputs are caller-owned; the library never frees caller memory;
+ *   - one context per host thread; contexts are independent;
+ *   - every call returns an lra_status: 0 = OK, > 0 = result valid with a
+ *     warning, < 0 = error and the result is invalid.
+ */
+#ifndef LRA_H
+#define LRA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LRA_OK = 0,
+    LRA_TOL_NOT_MET = 1,    /* tol not reached at k_max (best result returned)       */
+    LRA_MAXVOL_CAP = 2,     /* a maxvol call hit max_swaps                            */
+    LRA_NUMERICAL_RANK = 3, /* an LU pivot fell below 64 u max|strip|: k reduced      */
+    LRA_PENDING = 4,        /* lra_poll: the ticket has not completed yet             */
+    LRA_EINVAL = -1,        /* invalid argument                                       */
+    LRA_ERANK = -2,         /* exactly singular strip or generator (paper: FAILURE)   */
+    LRA_ENOMEM = -3,        /* device allocation failed                               */
+    LRA_EBUDGET = -4,       /* request exceeds the context's HBM budget               */
+    LRA_EDEVICE = -5,       /* HIP runtime error or device-side time-out              */
+    LRA_ENONFINITE = -6     /* NaN or Inf met in a strip                              */
+} lra_status;
+
+typedef enum { LRA_SRC_DENSE = 0, LRA_SRC_CAUCHY = 1, LRA_SRC_INVDIST = 2 } lra_src_kind;
+typedef enum { LRA_F32 = 0, LRA_F64 = 1 } lra_dtype;
+typedef enum { LRA_PREC_FP64 = 0, LRA_PREC_MIXED = 1 } lra_prec;
+
+/* Where the entries a(i,j) come from; the matrix is only ever touched entry
+ * by entry (Section 1.1: superfast methods read a tiny fraction of it).
+ *   DENSE  : a = device matrix of `dtype`; element (i,j) at a[i*lda + j]
+ *            (col_major = 0) or a[j*lda + i] (col_major = 1).
+ *   CAUCHY : x (m) and y (n) device vectors of `dtype`; a(i,j) = 1/(x_i - y_j).
+ *   INVDIST: x (m), y (n) points; a(i,j) = 1/|x_i - y_j|, 0 where they coincide.
+ * Differences of point coordinates are always formed in binary64. */
+typedef struct lra_source {
+    int32_t kind;        /* lra_src_kind */
+    int32_t dtype;       /* lra_dtype    */
+    const void* a;       /* DENSE: device pointer */
+    int64_t lda;
+    int32_t col_major;
+    int32_t reserved;
+    const void* x;       /* CAUCHY / INVDIST: device pointers */
+    const void* y;
+} lra_source;
+
+/* Options; lra_default_options() fills the defaults shown. */
+typedef struct lra_options {
+    double tau;                  /* maxvol tolerance: swap while max|C C_I^{-1}| > 1 + tau (0.01) */
+    int32_t k_max;               /* adaptive rank cap; <= k disables growth (0)             */
+    int32_t k_step;              /* rank increment (8)                                      */
+    int32_t max_swaps;           /* swaps per maxvol call; <= 0 means 4k + 64 (0)           */
+    int32_t warm_start;          /* 1: each step starts from the previous index set (1)     */
+    int32_t precision;           /* lra_prec: strips/basis in binary64, or binary32 (0)     */
+    int32_t sample_q, sample_s;  /* residual sample shape (64, 64; capped at m, n)          */
+    int32_t team_wgs;            /* workgroups per problem; 0 = autotuned (0)               */
+    int32_t reserved;
+    uint64_t seed;               /* SplitMix64 stream for the default draws below (0)       */
+    const int64_t* init_cols;    /* host, optional: candidate columns in draw order;
+                                    J0 = first k, rank growth takes the rest, skipping
+                                    columns already in J. NULL: draw min(n, 2 k_cap)
+                                    distinct columns from stream `seed`.                   */
+    int64_t n_init_cols;
+    const int64_t* sample_rows;  /* host, optional: Q (sample_q distinct rows); NULL: draw
+                                    from stream seed+1 and sort                             */
+    const int64_t* sample_cols;  /* host, optional: S (sample_s distinct cols); NULL: draw
+                                    from stream seed+2 and sort                             */
+} lra_options;
+
+/* Results.  I, J, G, U are caller-owned HOST arrays with capacity
+ * k_cap = max(k, k_max) (G, U: k_cap^2, row-major k x k for the final k).
+ * C_out / R_out are optional caller-owned DEVICE buffers receiving the CUR
+ * factors C = A[:,J] (m x k, column-major) and R = A[I,:] (k x n, row-major)
+ * in the strip precision (binary64 for LRA_PREC_FP64, else binary32). */
+typedef struct lra_result {
+    int64_t* I;
+    int64_t* J;
+    double* G;                   /* generator A[I,J] (binary64)                    */
+    double* U;                   /* nucleus A[I,J]^{-1} (binary64)                 */
+    void* C_out;
+    void* R_out;
+    int32_t k;                   /* final rank                                     */
+    int32_t status;              /* lra_status of this problem                     */
+    int32_t sweeps_done;
+    int32_t swaps_total;
+    int64_t entries_read;        /* entries touched: strips, generator, sample     */
+    double err_est_rel;          /* ||E_QS||_F / ||A_QS||_F                        */
+    double err_est_abs;          /* sqrt(mn/(qs)) ||E_QS||_F                       */
+    double err_mean, err_var;    /* sample mean / variance of the E_QS entries     */
+    double nucleus_cond1;        /* ||G||_1 ||U||_1                                */
+    double t_submit_us, t_start_us, t_end_us;  /* serving time stamps (host clock) */
+} lra_result;
+
+typedef struct lra_ctx lra_ctx;
+
+/* One far-field block of a hierarchical partition (Section 9: generators of
+ * neutered block columns are low-rank approximations of such blocks). */
+typedef struct lra_block {
+    lra_source src;              /* the block itself as a source (e.g. pointer offsets) */
+    int64_t m, n;
+    int32_t k, sweeps;
+    double tol;
+} lra_block;
+
+/* One request of the serving stream. */
+typedef struct lra_request {
+    lra_source src;
+    int64_t m, n;
+    int32_t k, sweeps;
+    double tol;
+    lra_options opts;
+    lra_result* result;          /* where lra_poll / lra_wait deliver the result */
+} lra_request;
+
+void lra_default_options(lra_options* opts);
+
+/* Create a context on the current HIP device.  stream: a hipStream_t (NULL =
+ * the null stream).  hbm_budget_bytes bounds the device workspace the
+ * context may hold (0 = no bound).  Errors: LRA_EDEVICE, LRA_ENOMEM. */
+lra_status lra_create(lra_ctx** ctx, void* stream, size_t hbm_budget_bytes);
+void lra_destroy(lra_ctx* ctx);
+
+/* C-A / CUR of one m x n matrix (Section 6.5): `sweeps` sweeps of one column
+ * step (maxvol on A[:,J] -> I) and one row step (maxvol on A[I,:]^T -> J)
+ * from J0, then the nucleus U = A[I,J]^{-1} and the sampled residual
+ * (Appendix F).  tol <= 0: exactly `sweeps` sweeps at rank k.  tol > 0:
+ * per rank level up to `sweeps` sweeps (stopping once a sweep leaves (I, J)
+ * unchanged); if the estimate exceeds tol and k < k_max, k_step new
+ * candidate columns are appended and the level restarts from a fresh LU.
+ * Requires 1 <= k <= min(m, n, 64), k_max <= 64.
+ * Errors: LRA_EINVAL, LRA_ERANK, LRA_ENONFINITE, LRA_ENOMEM, LRA_EBUDGET,
+ * LRA_EDEVICE. */
+lra_status lra_ca_cur(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k,
+                      int sweeps, double tol, const lra_options* opts, lra_result* result);
+
+/* The maxvol sub-algorithm alone on a tall device strip (m x k, column-major,
+ * leading dimension ld >= m, element type `dtype`): locally maximal-volume
+ * k x k row subset I (host, capacity k) such that every entry of
+ * strip * strip[I,:]^{-1} is at most 1 + tau in modulus.  init: optional host
+ * array of k distinct rows to start from (NULL: partial-pivot LU start).
+ * *swaps receives the number of swaps, *k_eff the rank used.  The strip is
+ * not modified.  Errors: LRA_EINVAL, LRA_ERANK, LRA_ENONFINITE, LRA_EDEVICE. */
+lra_status lra_maxvol(lra_ctx* ctx, const void* strip, int32_t dtype, int64_t m, int64_t ld,
+                      int k, double tau, int max_swaps, const int64_t* init, int64_t* I,
+                      int* swaps, int* k_eff);
+
+/* Many independent C-A / CUR problems (e.g. all admissible blocks of a
+ * hierarchical partition, Section 9) in one persistent launch.  Each block
+ * uses its own k, sweeps, tol; `opts` applies to all (init_cols /
+ * sample_rows / sample_cols must be NULL: each block draws from stream
+ * opts->seed + block index).  results[b] as for lra_ca_cur; the call returns
+ * the most severe per-block status. */
+lra_status lra_ca_cur_batched(lra_ctx* ctx, const lra_block* blocks, int nblocks,
+                              const lra_options* opts, lra_result* results);
+
+/* Serving: submit a request (copied; its arrays must stay valid until it
+ * completes); the context's scheduler admits it once its workspace fits the
+ * HBM budget and a slot is free, and advances all admitted requests together
+ * (continuous batching).  Errors at submit: LRA_EINVAL, LRA_EBUDGET (larger
+ * than the whole budget). */
+lra_status lra_submit(lra_ctx* ctx, const lra_request* req, uint64_t* ticket);
+/* Advance the scheduler once; returns LRA_PENDING or the request's status. */
+lra_status lra_poll(lra_ctx* ctx, uint64_t ticket);
+/* Advance until the ticket completes; returns its status. */
+lra_status lra_wait(lra_ctx* ctx, uint64_t ticket);
+
+const char* lra_status_str(lra_status s);
+/* Library version string. */
+const char* lra_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,392 @@
+"""Thin ctypes binding of the gfx950 C-A / CUR library (include/lra.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  Device memory and streams come from PyTorch tensors; the
+library never sees a torch type.  If the built library is missing the
+binding raises -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "liblra.so")
+
+# status codes (lra_status)
+OK, TOL_NOT_MET, MAXVOL_CAP, NUMERICAL_RANK, PENDING = 0, 1, 2, 3, 4
+EINVAL, ERANK, ENOMEM, EBUDGET, EDEVICE, ENONFINITE = -1, -2, -3, -4, -5, -6
+SRC_DENSE, SRC_CAUCHY, SRC_INVDIST = 0, 1, 2
+F32, F64 = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+
+# every entry point declared in include/lra.h
+EXPORTS = ["lra_default_options", "lra_create", "lra_destroy", "lra_ca_cur", "lra_maxvol",
+           "lra_ca_cur_batched", "lra_submit", "lra_poll", "lra_wait", "lra_status_str",
+           "lra_version"]
+
+
+class LraError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+        self.status = status
+
+
+class Source(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("a", C.c_void_p), ("lda", C.c_int64),
+                ("col_major", C.c_int32), ("reserved", C.c_int32), ("x", C.c_void_p),
+                ("y", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("tau", C.c_double), ("k_max", C.c_int32), ("k_step", C.c_int32),
+                ("max_swaps", C.c_int32), ("warm_start", C.c_int32), ("precision", C.c_int32),
+                ("sample_q", C.c_int32), ("sample_s", C.c_int32), ("team_wgs", C.c_int32),
+                ("reserved", C.c_int32), ("seed", C.c_uint64), ("init_cols", C.c_void_p),
+                ("n_init_cols", C.c_int64), ("sample_rows", C.c_void_p),
+                ("sample_cols", C.c_void_p)]
+
+
+class ResultC(C.Structure):
+    _fields_ = [("I", C.c_void_p), ("J", C.c_void_p), ("G", C.c_void_p), ("U", C.c_void_p),
+                ("C_out", C.c_void_p), ("R_out", C.c_void_p), ("k", C.c_int32),
+                ("status", C.c_int32), ("sweeps_done", C.c_int32), ("swaps_total", C.c_int32),
+                ("entries_read", C.c_int64), ("err_est_rel", C.c_double),
+                ("err_est_abs", C.c_double), ("err_mean", C.c_double), ("err_var", C.c_double),
+                ("nucleus_cond1", C.c_double), ("t_submit_us", C.c_double),
+                ("t_start_us", C.c_double), ("t_end_us", C.c_double)]
+
+
+class Block(C.Structure):
+    _fields_ = [("src", Source), ("m", C.c_int64), ("n", C.c_int64), ("k", C.c_int32),
+                ("sweeps", C.c_int32), ("tol", C.c_double)]
+
+
+class RequestC(C.Structure):
+    _fields_ = [("src", Source), ("m", C.c_int64), ("n", C.c_int64), ("k", C.c_int32),
+                ("sweeps", C.c_int32), ("tol", C.c_double), ("opts", Options),
+                ("result", C.POINTER(ResultC))]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblra.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1611_01391_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.lra_default_options.argtypes = [C.POINTER(Options)]
+        L.lra_default_options.restype = None
+        L.lra_create.argtypes = [C.POINTER(P), P, C.c_size_t]
+        L.lra_create.restype = C.c_int
+        L.lra_destroy.argtypes = [P]
+        L.lra_destroy.restype = None
+        L.lra_ca_cur.argtypes = [P, C.POINTER(Source), C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                 C.c_double, C.POINTER(Options), C.POINTER(ResultC)]
+        L.lra_ca_cur.restype = C.c_int
+        L.lra_maxvol.argtypes = [P, P, C.c_int32, C.c_int64, C.c_int64, C.c_int, C.c_double,
+                                 C.c_int, P, P, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.lra_maxvol.restype = C.c_int
+        L.lra_ca_cur_batched.argtypes = [P, C.POINTER(Block), C.c_int, C.POINTER(Options),
+                                         C.POINTER(ResultC)]
+        L.lra_ca_cur_batched.restype = C.c_int
+        L.lra_submit.argtypes = [P, C.POINTER(RequestC), C.POINTER(C.c_uint64)]
+        L.lra_submit.restype = C.c_int
+        L.lra_poll.argtypes = [P, C.c_uint64]
+        L.lra_poll.restype = C.c_int
+        L.lra_wait.argtypes = [P, C.c_uint64]
+        L.lra_wait.restype = C.c_int
+        L.lra_status_str.argtypes = [C.c_int]
+        L.lra_status_str.restype = C.c_char_p
+        L.lra_version.argtypes = []
+        L.lra_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def status_str(s: int) -> str:
+    return lib().lra_status_str(int(s)).decode()
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    lib().lra_default_options(C.byref(o))
+    for key, val in kw.items():
+        if not hasattr(o, key):
+            raise TypeError(f"unknown option {key}")
+        setattr(o, key, val)
+    return o
+
+
+# ---------------------------------------------------------------------------
+# sources over torch device tensors
+# ---------------------------------------------------------------------------
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError("sources must be float32 or float64 tensors")
+
+
+def _require_cuda(t):
+    if not t.is_cuda:
+        raise TypeError("sources must live in device memory (a cuda tensor)")
+
+
+@dataclass
+class DeviceSource:
+    struct: Source
+    m: int
+    n: int
+    keep: tuple = ()
+
+
+def dense(A, col_major: bool = False) -> DeviceSource:
+    """A dense m x n device matrix (row-major tensor, or a column-major view)."""
+    _require_cuda(A)
+    m, n = A.shape
+    if col_major:
+        if A.stride(0) != 1:
+            raise ValueError("col_major source needs stride(0) == 1")
+        lda = A.stride(1)
+    else:
+        if A.stride(1) != 1:
+            raise ValueError("row-major source needs stride(1) == 1")
+        lda = A.stride(0)
+    s = Source(SRC_DENSE, _dtype_code(A), A.data_ptr(), lda, 1 if col_major else 0, 0, None, None)
+    return DeviceSource(s, m, n, (A,))
+
+
+def cauchy(x, y) -> DeviceSource:
+    """a_ij = 1 / (x_i - y_j) for device vectors x (m) and y (n)."""
+    _require_cuda(x)
+    _require_cuda(y)
+    if x.dtype != y.dtype or not x.is_contiguous() or not y.is_contiguous():
+        raise ValueError("x and y must be contiguous and of one dtype")
+    s = Source(SRC_CAUCHY, _dtype_code(x), None, 0, 0, 0, x.data_ptr(), y.data_ptr())
+    return DeviceSource(s, x.numel(), y.numel(), (x, y))
+
+
+def invdist(x, y) -> DeviceSource:
+    """a_ij = 1 / |x_i - y_j| (0 where equal) for device point sets x, y."""
+    src = cauchy(x, y)
+    src.struct.kind = SRC_INVDIST
+    return src
+
+
+# ---------------------------------------------------------------------------
+# results
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Result:
+    status: int
+    k: int
+    I: np.ndarray
+    J: np.ndarray
+    G: np.ndarray
+    U: np.ndarray
+    sweeps_done: int
+    swaps_total: int
+    entries_read: int
+    err_est_rel: float
+    err_est_abs: float
+    err_mean: float
+    err_var: float
+    nucleus_cond1: float
+    t_submit_us: float = 0.0
+    t_start_us: float = 0.0
+    t_end_us: float = 0.0
+    C: object = None
+    R: object = None
+
+
+class _ResultBuf:
+    def __init__(self, kcap: int):
+        self.kcap = kcap
+        self.I = np.zeros(kcap, dtype=np.int64)
+        self.J = np.zeros(kcap, dtype=np.int64)
+        self.G = np.zeros(kcap * kcap)
+        self.U = np.zeros(kcap * kcap)
+        self.c = ResultC()
+        self.c.I = self.I.ctypes.data
+        self.c.J = self.J.ctypes.data
+        self.c.G = self.G.ctypes.data
+        self.c.U = self.U.ctypes.data
+
+    def to_result(self, C_t=None, R_t=None) -> Result:
+        r = self.c
+        k = max(0, r.k)
+        return Result(r.status, k, self.I[:k].copy(), self.J[:k].copy(),
+                      self.G[:k * k].reshape(k, k).copy(), self.U[:k * k].reshape(k, k).copy(),
+                      r.sweeps_done, r.swaps_total, r.entries_read, r.err_est_rel, r.err_est_abs,
+                      r.err_mean, r.err_var, r.nucleus_cond1, r.t_submit_us, r.t_start_us,
+                      r.t_end_us, C_t, R_t)
+
+
+def _i64(a) -> Optional[np.ndarray]:
+    if a is None:
+        return None
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int64))
+
+
+# ---------------------------------------------------------------------------
+# context
+# ---------------------------------------------------------------------------
+
+class Context:
+    """An lra_ctx bound to the current device and torch's current stream."""
+
+    def __init__(self, stream=None, hbm_budget_bytes: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the library runs on gfx950 only")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._h = C.c_void_p()
+        st = lib().lra_create(C.byref(self._h), C.c_void_p(stream.cuda_stream), hbm_budget_bytes)
+        if st != OK:
+            raise LraError(st, "lra_create")
+        self._keep = {}
+
+    def close(self):
+        if self._h:
+            lib().lra_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- one problem ------------------------------------------------------
+    def ca_cur(self, src: DeviceSource, k: int, sweeps: int, tol: float = 0.0, *,
+               init_cols=None, sample_rows=None, sample_cols=None, factors: bool = False,
+               raise_on_error: bool = True, **opts) -> Result:
+        import torch
+        o = default_options(**opts)
+        cand, Q, S = _i64(init_cols), _i64(sample_rows), _i64(sample_cols)
+        if cand is not None:
+            o.init_cols = cand.ctypes.data
+            o.n_init_cols = len(cand)
+        if Q is not None:
+            o.sample_rows = Q.ctypes.data
+            o.sample_q = len(Q)
+        if S is not None:
+            o.sample_cols = S.ctypes.data
+            o.sample_s = len(S)
+        kcap = max(k, o.k_max)
+        buf = _ResultBuf(kcap)
+        C_t = R_t = None
+        if factors:
+            dt = torch.float64 if o.precision == PREC_FP64 else torch.float32
+            dev = src.keep[0].device
+            C_t = torch.empty(kcap * src.m, dtype=dt, device=dev)
+            R_t = torch.empty(kcap * src.n, dtype=dt, device=dev)
+            buf.c.C_out = C_t.data_ptr()
+            buf.c.R_out = R_t.data_ptr()
+        st = lib().lra_ca_cur(self._h, C.byref(src.struct), src.m, src.n, int(k), int(sweeps),
+                              float(tol), C.byref(o), C.byref(buf.c))
+        if st < 0 and raise_on_error:
+            raise LraError(st, "lra_ca_cur")
+        if st < 0:
+            buf.c.status = st
+        res = buf.to_result()
+        if factors and st >= 0:
+            kk = res.k
+            res.C = C_t[:kk * src.m].view(kk, src.m).t()       # m x k (column-major)
+            res.R = R_t[:kk * src.n].view(kk, src.n)           # k x n (row-major)
+        return res
+
+    # -- maxvol alone -----------------------------------------------------
+    def maxvol(self, strip, tau: float = 0.01, init=None, max_swaps: int = 0):
+        """maxvol on an m x k device strip (any layout with unit row stride of
+        a column-major view, i.e. strip.stride(0) == 1)."""
+        _require_cuda(strip)
+        m, k = strip.shape
+        if strip.stride(0) != 1:
+            strip = strip.t().contiguous().t()
+        ld = strip.stride(1) if k > 1 else m
+        I = np.zeros(k, dtype=np.int64)
+        init_a = _i64(init)
+        sw = C.c_int(0)
+        ke = C.c_int(0)
+        st = lib().lra_maxvol(self._h, strip.data_ptr(), _dtype_code(strip), m, ld, int(k),
+                              float(tau), int(max_swaps),
+                              None if init_a is None else init_a.ctypes.data, I.ctypes.data,
+                              C.byref(sw), C.byref(ke))
+        if st < 0:
+            raise LraError(st, "lra_maxvol")
+        return dict(I=I[:ke.value].copy(), swaps=sw.value, k_eff=ke.value, status=st)
+
+    # -- batched ----------------------------------------------------------
+    def ca_cur_batched(self, blocks: Sequence[tuple], raise_on_error: bool = True, **opts):
+        """blocks: sequence of (DeviceSource, k, sweeps, tol)."""
+        o = default_options(**opts)
+        nb = len(blocks)
+        arr = (Block * max(1, nb))()
+        bufs = []
+        for b, (src, k, sweeps, tol) in enumerate(blocks):
+            arr[b].src = src.struct
+            arr[b].m = src.m
+            arr[b].n = src.n
+            arr[b].k = int(k)
+            arr[b].sweeps = int(sweeps)
+            arr[b].tol = float(tol)
+            bufs.append(_ResultBuf(max(int(k), o.k_max)))
+        res_arr = (ResultC * max(1, nb))()
+        for b in range(nb):
+            res_arr[b] = bufs[b].c
+        st = lib().lra_ca_cur_batched(self._h, arr, nb, C.byref(o), res_arr)
+        if st < 0 and raise_on_error and st not in (ERANK, ENONFINITE):
+            raise LraError(st, "lra_ca_cur_batched")
+        out = []
+        for b in range(nb):
+            bufs[b].c = res_arr[b]
+            out.append(bufs[b].to_result())
+        return st, out
+
+    # -- serving ----------------------------------------------------------
+    def submit(self, src: DeviceSource, k: int, sweeps: int, tol: float = 0.0, **opts) -> int:
+        o = default_options(**opts)
+        buf = _ResultBuf(max(int(k), o.k_max))
+        req = RequestC()
+        req.src = src.struct
+        req.m = src.m
+        req.n = src.n
+        req.k = int(k)
+        req.sweeps = int(sweeps)
+        req.tol = float(tol)
+        req.opts = o
+        req.result = C.pointer(buf.c)
+        t = C.c_uint64(0)
+        st = lib().lra_submit(self._h, C.byref(req), C.byref(t))
+        if st < 0:
+            raise LraError(st, "lra_submit")
+        self._keep[t.value] = (buf, src)
+        return t.value
+
+    def poll(self, ticket: int):
+        st = lib().lra_poll(self._h, ticket)
+        if st == PENDING:
+            return None
+        buf, _ = self._keep.pop(ticket)
+        return buf.to_result()
+
+    def wait(self, ticket: int) -> Result:
+        lib().lra_wait(self._h, ticket)
+        buf, _ = self._keep.pop(ticket)
+        return buf.to_result()

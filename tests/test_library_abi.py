@@ -1,0 +1,50 @@
+"""Host-side checks of the C ABI library (no GPU needed): it loads, exports
+every symbol that include/lra.h declares, and its argument checks reject
+invalid calls before touching a device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1611_01391_amd import lra
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lra.h")).read()
+    return sorted(set(re.findall(r"\b(lra_[a-z_]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(lra.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    L = lra.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_status_strings_and_version():
+    assert lra.status_str(lra.OK) == "ok"
+    assert "invalid" in lra.status_str(lra.EINVAL)
+    assert lra.lib().lra_version().decode().startswith("lra-gfx950")
+
+
+def test_default_options():
+    o = lra.default_options()
+    assert o.tau == 0.01 and o.k_step == 8 and o.warm_start == 1 and o.sample_q == 64
+
+
+def test_create_rejects_null():
+    assert lra.lib().lra_create(None, None, 0) == lra.EINVAL
+
+
+def test_calls_reject_null_context():
+    L = lra.lib()
+    res = lra.ResultC()
+    src = lra.Source()
+    assert L.lra_ca_cur(None, C.byref(src), 10, 10, 2, 1, 0.0, None, C.byref(res)) == lra.EINVAL
+    assert L.lra_ca_cur_batched(None, None, 1, None, None) == lra.EINVAL
