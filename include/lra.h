@@ -87,7 +87,7 @@ typedef struct lra_options {
     int32_t max_swaps;           /* swaps per maxvol call; <= 0 means 4k + 64 (0)           */
     int32_t warm_start;          /* 1: each step starts from the previous index set (1)     */
     int32_t precision;           /* lra_prec: strips/basis in binary64, or binary32 (0)     */
-    int32_t sample_q, sample_s;  /* residual sample shape (64, 64; capped at m, n)          */
+    int32_t sample_q, sample_s;  /* residual sample shape, each 1..64 (64, 64; capped at m, n) */
     int32_t team_wgs;            /* workgroups per problem; 0 = autotuned (0)               */
     int32_t reserved;
     uint64_t seed;               /* SplitMix64 stream for the default draws below (0)       */
@@ -198,6 +198,20 @@ lra_status lra_submit(lra_ctx* ctx, const lra_request* req, uint64_t* ticket);
 lra_status lra_poll(lra_ctx* ctx, uint64_t ticket);
 /* Advance until the ticket completes; returns its status. */
 lra_status lra_wait(lra_ctx* ctx, uint64_t ticket);
+
+/* Kernel timing of a context.  With timing enabled, HIP events on the
+ * context's stream bracket every engine launch; engine_ms_total accumulates
+ * their elapsed times and last_engine_ms holds the latest one. */
+typedef struct lra_stats {
+    int64_t launches;            /* engine launches since creation or reset */
+    double engine_ms_total;      /* summed event time (timing enabled only)  */
+    double last_engine_ms;
+    int32_t last_grid;           /* workgroups of the latest launch          */
+    int32_t last_teams;          /* teams of the latest launch               */
+} lra_stats;
+/* enable: 1 on, 0 off; reset: zero the counters. */
+lra_status lra_set_timing(lra_ctx* ctx, int enable, int reset);
+lra_status lra_get_stats(lra_ctx* ctx, lra_stats* out);
 
 const char* lra_status_str(lra_status s);
 /* Library version string. */

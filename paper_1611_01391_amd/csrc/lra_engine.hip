@@ -3,11 +3,12 @@
 // One persistent kernel runs whole C-A / CUR problems.  A problem is owned by
 // a *team* of workgroups; every pivot decision (a partial-pivot LU step or a
 // maxvol swap) is one team-wide argmax: each workgroup reduces its rows
-// (wavefront shuffles, then LDS), publishes its best key and candidate row in
+// (DPP wavefront max, then LDS), publishes its best key and candidate row in
 // a slot in global memory, and after one team barrier every workgroup reduces
 // the slots and reads the winning row.  A team of one workgroup needs no
 // barrier at all.  A workgroup keeps its rows of the strip in LDS when they
-// fit, else in a global strip buffer.
+// fit, else in a global strip buffer.  The basis product C * Chat^{-1} runs
+// on the matrix cores (16x16x4 MFMA, binary64 or binary32).
 //
 // Method (arXiv:1611.01391): C-A iterations of Section 6.5 in the dual order
 // of Remark rec-atnsr (vertical step first); each step picks a k x k
@@ -26,22 +27,23 @@ namespace lra {
 
 constexpr int NWAVE = NT / 64;
 #define AGENT __HIP_MEMORY_SCOPE_AGENT
+#define DI __device__ __forceinline__
 
 // ----------------------------------------------------------------------------
 // entries
 // ----------------------------------------------------------------------------
 
-__device__ __forceinline__ double load_elem(const void* p, int dtype, int64_t off)
+DI double load_elem(const void* p, int dtype, int64_t off)
 {
     return dtype == 0 ? (double)((const float*)p)[off] : ((const double*)p)[off];
 }
 
 // Entry from a coordinate difference d (binary64): 1/d or 1/|d| (0 at d = 0).
 template <typename T>
-__device__ __forceinline__ T kernel_entry(int kind, double d);
+DI T kernel_entry(int kind, double d);
 
 template <>
-__device__ __forceinline__ double kernel_entry<double>(int kind, double d)
+DI double kernel_entry<double>(int kind, double d)
 {
     if (kind == 1) return 1.0 / d;
     double ad = fabs(d);
@@ -49,7 +51,7 @@ __device__ __forceinline__ double kernel_entry<double>(int kind, double d)
 }
 
 template <>
-__device__ __forceinline__ float kernel_entry<float>(int kind, double d)
+DI float kernel_entry<float>(int kind, double d)
 {
     if (kind == 1) return 1.0f / (float)d;
     double ad = fabs(d);
@@ -57,73 +59,96 @@ __device__ __forceinline__ float kernel_entry<float>(int kind, double d)
 }
 
 template <typename T>
-__device__ __forceinline__ T dense_entry(const DevSource& s, int64_t i, int64_t j);
+DI T dense_entry(const DevSource& s, int64_t i, int64_t j);
 
 template <>
-__device__ __forceinline__ double dense_entry<double>(const DevSource& s, int64_t i, int64_t j)
+DI double dense_entry<double>(const DevSource& s, int64_t i, int64_t j)
 {
     int64_t off = s.col_major ? j * s.lda + i : i * s.lda + j;
     return load_elem(s.a, s.dtype, off);
 }
 
 template <>
-__device__ __forceinline__ float dense_entry<float>(const DevSource& s, int64_t i, int64_t j)
+DI float dense_entry<float>(const DevSource& s, int64_t i, int64_t j)
 {
     int64_t off = s.col_major ? j * s.lda + i : i * s.lda + j;
     return s.dtype == 0 ? ((const float*)s.a)[off] : (float)((const double*)s.a)[off];
 }
 
 template <typename T>
-__device__ __forceinline__ T entry_t(const DevSource& s, int64_t i, int64_t j)
+DI T entry_t(const DevSource& s, int64_t i, int64_t j)
 {
     if (s.kind == 0) return dense_entry<T>(s, i, j);
     double d = load_elem(s.x, s.dtype, i) - load_elem(s.y, s.dtype, j);
     return kernel_entry<T>(s.kind, d);
 }
 
-__device__ __forceinline__ double entry64(const DevSource& s, int64_t i, int64_t j)
-{
-    return entry_t<double>(s, i, j);
-}
+DI double entry64(const DevSource& s, int64_t i, int64_t j) { return entry_t<double>(s, i, j); }
 
 // ----------------------------------------------------------------------------
-// argmax keys: larger |value|, then smaller row, then smaller column
+// argmax keys: (hi, lo) compared lexicographically; hi = bit pattern of a
+// non-negative binary64 |value| (ordered like the value), lo = ~(row << 8 |
+// col), so ties go to the smaller row, then the smaller column.
 // ----------------------------------------------------------------------------
 
-struct Key {
-    double v;
-    int64_t r;
-    int32_t c;
-    int32_t w;  // owning workgroup (carried, not compared)
+struct K2 {
+    uint64_t hi, lo;
 };
 
-__device__ __forceinline__ Key key_none()
+DI K2 k2_none() { return K2{0ull, 0ull}; }
+
+DI bool k2_better(const K2& a, const K2& b) { return a.hi > b.hi || (a.hi == b.hi && a.lo > b.lo); }
+
+DI K2 k2_make(double absv, int64_t row, int col)
 {
-    Key k;
-    k.v = -1.0;
-    k.r = INT64_MAX;
-    k.c = INT32_MAX;
-    k.w = -1;
-    return k;
+    return K2{(uint64_t)__double_as_longlong(absv), ~(((uint64_t)row << 8) | (uint64_t)col)};
 }
 
-__device__ __forceinline__ bool kbetter(const Key& a, const Key& b)
+DI int64_t k2_row(const K2& k) { return (int64_t)((~k.lo) >> 8); }
+DI int k2_col(const K2& k) { return (int)((~k.lo) & 0xFFull); }
+DI double k2_val(const K2& k) { return __longlong_as_double((long long)k.hi); }
+
+template <int CTRL, int ROWMASK>
+DI uint64_t dpp64(uint64_t v)
 {
-    return a.v > b.v || (a.v == b.v && (a.r < b.r || (a.r == b.r && a.c < b.c)));
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROWMASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROWMASK, 0xF, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
 }
 
-__device__ __forceinline__ Key wave_reduce(Key k)
+DI uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+DI uint64_t readlane64(uint64_t v, int lane)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        Key o;
-        o.v = __shfl_xor(k.v, off);
-        o.r = __shfl_xor(k.r, off);
-        o.c = __shfl_xor(k.c, off);
-        o.w = __shfl_xor(k.w, off);
-        if (kbetter(o, k)) k = o;
-    }
-    return k;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Maximum over the 64 lanes of a full wavefront (row shifts 1, 2, 4, 8 within
+// each row of 16 lanes, then the row-15 and row-31 broadcasts; lane 63 ends
+// with the maximum, which is then read as a uniform value).
+DI uint64_t wave_max_u64(uint64_t v)
+{
+    v = umax64(v, dpp64<0x111, 0xF>(v));
+    v = umax64(v, dpp64<0x112, 0xF>(v));
+    v = umax64(v, dpp64<0x114, 0xF>(v));
+    v = umax64(v, dpp64<0x118, 0xF>(v));
+    v = umax64(v, dpp64<0x142, 0xA>(v));
+    v = umax64(v, dpp64<0x143, 0xC>(v));
+    return readlane64(v, 63);
+}
+
+DI K2 wave_argmax(const K2& k)
+{
+    const uint64_t mh = wave_max_u64(k.hi);
+    const uint64_t ball = __ballot(k.hi == mh);
+    uint64_t lo;
+    if (__popcll(ball) == 1)
+        lo = readlane64(k.lo, __ffsll((unsigned long long)ball) - 1);
+    else
+        lo = wave_max_u64(k.hi == mh ? k.lo : 0ull);
+    return K2{mh, lo};
 }
 
 // ----------------------------------------------------------------------------
@@ -133,41 +158,23 @@ __device__ __forceinline__ Key wave_reduce(Key k)
 template <typename T, int KMAX>
 struct Smem {
     int64_t I[KMAX], J[KMAX], prevI[KMAX], prevJ[KMAX];
-    double LU[KMAX * KMAX];   // k x k work matrix (row stride KMAX)
+    double AUG[KMAX * 2 * KMAX];  // [M | right-hand sides], row stride 2 KMAX (T view for the strip)
+    double fcol[KMAX];            // multipliers / column of U of the current step
+    double diag[KMAX];            // pivots of the current factorisation
     double red[NT];           // fixed-order reductions
     double pts[KMAX];         // coordinates of the fixed index set (generated sources)
     T g[KMAX];                // swap update vector
     T pay[KMAX];              // candidate / winning row
     int32_t perm[KMAX];
-    Key kred[NWAVE];
-    Key win;
+    K2 kred[2][NWAVE];
     // problem state (mirrors TaskState)
     int32_t k, phase, sweep_in_level, status, warn, have_I, had_I_sweep, k_sweep_start;
     int32_t swaps_total, sweeps_done, phases_run;
     int64_t cand_next, entries_read;
     double est_rel, est_abs, mean, var, cond1;
-    int32_t flag, fetch, ok, kstep_res;
-    double thresh;
+    int32_t flag, fetch, ok, pivp;
+    double minpiv;
 };
-
-template <typename T, int KMAX>
-__device__ __forceinline__ Key block_reduce(Key k, Smem<T, KMAX>& sm)
-{
-    k = wave_reduce(k);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) sm.kred[w] = k;
-    __syncthreads();
-    Key b = sm.kred[0];
-#pragma unroll
-    for (int i = 1; i < NWAVE; ++i)
-        if (kbetter(sm.kred[i], b)) b = sm.kred[i];
-    __syncthreads();
-    return b;
-}
-
-// ----------------------------------------------------------------------------
-// team synchronisation
-// ----------------------------------------------------------------------------
 
 struct Team {
     uint8_t* ctl;
@@ -175,20 +182,58 @@ struct Team {
     int rank;
     uint32_t epoch;
     bool failed;
+    int tog;  // LDS double-buffer selector of block_argmax
     uint32_t* err;
     int64_t timeout;
+    uint64_t* trace;
+    int32_t trace_cap;
+    int32_t trace_n;
 };
 
-__device__ __forceinline__ uint8_t* slot_ptr(const Team& tm, int parity, int wg)
+// Workgroup argmax: wavefront maxima, then one LDS exchange.  The two LDS
+// banks alternate between calls, so one barrier per call suffices.
+template <typename T, int KMAX>
+DI K2 block_argmax(const K2& k, Smem<T, KMAX>& sm, Team& tm)
+{
+    const K2 w = wave_argmax(k);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) sm.kred[tm.tog][wv] = w;
+    __syncthreads();
+    K2 b = sm.kred[tm.tog][0];
+#pragma unroll
+    for (int i = 1; i < NWAVE; ++i)
+        if (k2_better(sm.kred[tm.tog][i], b)) b = sm.kred[tm.tog][i];
+    tm.tog ^= 1;
+    return b;
+}
+
+// Optional event trace: thread 0 of the first workgroup of team 0 records
+// (event, wall clock) pairs with plain stores; the count goes to trace[0].
+DI void trace_ev(Team& tm, int ev, int64_t arg)
+{
+    if (tm.trace == nullptr || tm.rank != 0 || threadIdx.x != 0) return;
+    const int idx = tm.trace_n++;
+    if (idx >= tm.trace_cap) return;
+    tm.trace[1 + 2 * idx] = ((uint64_t)ev << 56) | ((uint64_t)arg & 0x00FFFFFFFFFFFFFFull);
+    tm.trace[2 + 2 * idx] = wall_clock64();
+    tm.trace[0] = (uint64_t)(idx + 1);
+}
+
+// ----------------------------------------------------------------------------
+// team synchronisation.  Only wavefront 0 of a workgroup writes data that
+// other workgroups read (slots, state); thread 0's release on the arrival
+// counter publishes them, its acquire plus the workgroup barrier makes the
+// other workgroups' data visible.
+// ----------------------------------------------------------------------------
+
+DI uint8_t* slot_ptr(const Team& tm, int parity, int wg)
 {
     return tm.ctl + CTL_HDR + (int64_t)(parity * tm.size + wg) * SLOT_STRIDE;
 }
 
-// Team barrier on a monotone arrival counter; thread 0 waits with a time-out.
 template <typename T, int KMAX>
-__device__ void team_barrier(Team& tm, Smem<T, KMAX>& sm)
+DI void team_barrier(Team& tm, Smem<T, KMAX>& sm)
 {
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t* ctr = (uint32_t*)tm.ctl;
@@ -213,9 +258,10 @@ __device__ void team_barrier(Team& tm, Smem<T, KMAX>& sm)
 
 // Team-wide argmax: publish this workgroup's best key and its candidate row
 // (sm.pay[0..n)), then every workgroup reduces all slots and loads the
-// winning row into sm.pay.  With one workgroup the local result is final.
+// winning row (owner = row / rows_per_wg) into sm.pay.  With one workgroup
+// the local result is final.
 template <typename T, int KMAX>
-__device__ Key team_argmax(Team& tm, Smem<T, KMAX>& sm, Key mine, int n)
+DI K2 team_argmax(Team& tm, Smem<T, KMAX>& sm, const K2& mine, int n, int64_t rows_per_wg)
 {
     if (tm.size == 1) return mine;
     const int par = tm.epoch & 1;
@@ -224,28 +270,26 @@ __device__ Key team_argmax(Team& tm, Smem<T, KMAX>& sm, Key mine, int n)
     if (threadIdx.x < n)
         __hip_atomic_store(mypay + threadIdx.x, (double)sm.pay[threadIdx.x], __ATOMIC_RELAXED, AGENT);
     if (threadIdx.x == 0) {
-        __hip_atomic_store((double*)my, mine.v, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store((int64_t*)(my + 8), mine.r, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store((int32_t*)(my + 16), mine.c, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store((uint64_t*)my, mine.hi, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store((uint64_t*)(my + 8), mine.lo, __ATOMIC_RELAXED, AGENT);
     }
     team_barrier(tm, sm);
-    if (tm.failed) return key_none();
-    Key best = key_none();
-    for (int w = threadIdx.x; w < tm.size; w += NT) {
-        const uint8_t* sp = slot_ptr(tm, par, w);
-        Key o;
-        o.v = __hip_atomic_load((double*)sp, __ATOMIC_RELAXED, AGENT);
-        o.r = __hip_atomic_load((int64_t*)(sp + 8), __ATOMIC_RELAXED, AGENT);
-        o.c = __hip_atomic_load((int32_t*)(sp + 16), __ATOMIC_RELAXED, AGENT);
-        o.w = w;
-        if (kbetter(o, best)) best = o;
+    if (tm.failed) return k2_none();
+    K2 o = k2_none();
+    if (threadIdx.x < tm.size) {
+        const uint8_t* sp = slot_ptr(tm, par, threadIdx.x);
+        o.hi = __hip_atomic_load((uint64_t*)sp, __ATOMIC_RELAXED, AGENT);
+        o.lo = __hip_atomic_load((uint64_t*)(sp + 8), __ATOMIC_RELAXED, AGENT);
     }
-    best = block_reduce(best, sm);
-    if (threadIdx.x < n) {
-        const double* wp = (const double*)(slot_ptr(tm, par, best.w) + 32);
-        sm.pay[threadIdx.x] = (T)__hip_atomic_load(wp + threadIdx.x, __ATOMIC_RELAXED, AGENT);
+    const K2 best = block_argmax(o, sm, tm);
+    if (n > 0) {
+        const int w = (int)(k2_row(best) / rows_per_wg);
+        if (threadIdx.x < n) {
+            const double* wp = (const double*)(slot_ptr(tm, par, w) + 32);
+            sm.pay[threadIdx.x] = (T)__hip_atomic_load(wp + threadIdx.x, __ATOMIC_RELAXED, AGENT);
+        }
+        __syncthreads();
     }
-    __syncthreads();
     return best;
 }
 
@@ -262,99 +306,238 @@ struct Rows {
 };
 
 // Gather rows [r0, r0 + nrows) of the strip: column step A[:, F], row step
-// A[F, :]^T.  Physical column c of the slice receives logical column
-// cmap[c] (cmap == nullptr: identity).  Returns this thread's max |entry|
-// (+inf if an entry is not finite).
+// A[F, :]^T.  Returns this thread's max |entry| (+inf if an entry is not
+// finite).
 template <typename T, int KMAX>
-__device__ double gather_rows(const DevSource& s, int transpose, const Smem<T, KMAX>& sm,
-                              const int64_t* F, const int32_t* cmap, int k, const Rows<T>& rw)
+DI double gather_rows(const DevSource& s, int transpose, const Smem<T, KMAX>& sm, const int64_t* F, int k,
+                      const Rows<T>& rw)
 {
+    constexpr int CH = KMAX < 32 ? KMAX : 32;  // columns loaded together
     double lmax = 0.0;
     for (int r = threadIdx.x; r < rw.nrows; r += NT) {
         const int64_t gi = rw.r0 + r;
-        T v[KMAX];
-        if (s.kind == 0) {
+        const double own = s.kind == 0 ? 0.0 : (transpose ? load_elem(s.y, s.dtype, gi) : load_elem(s.x, s.dtype, gi));
+        for (int c0 = 0; c0 < k; c0 += CH) {
+            T v[CH];
 #pragma unroll
-            for (int c = 0; c < KMAX; ++c)
+            for (int cc = 0; cc < CH; ++cc) {
+                const int c = c0 + cc;
                 if (c < k) {
-                    const int64_t f = F[cmap ? cmap[c] : c];
-                    v[c] = transpose ? dense_entry<T>(s, f, gi) : dense_entry<T>(s, gi, f);
+                    if (s.kind == 0) v[cc] = transpose ? dense_entry<T>(s, F[c], gi) : dense_entry<T>(s, gi, F[c]);
+                    else v[cc] = kernel_entry<T>(s.kind, transpose ? sm.pts[c] - own : own - sm.pts[c]);
                 }
-        } else {
-            const double own = transpose ? load_elem(s.y, s.dtype, gi) : load_elem(s.x, s.dtype, gi);
-#pragma unroll
-            for (int c = 0; c < KMAX; ++c)
-                if (c < k) {
-                    const double pt = sm.pts[cmap ? cmap[c] : c];
-                    v[c] = kernel_entry<T>(s.kind, transpose ? pt - own : own - pt);
-                }
-        }
-#pragma unroll
-        for (int c = 0; c < KMAX; ++c)
-            if (c < k) {
-                double a = fabs((double)v[c]);
-                if (!(a <= 1.0e308)) a = INFINITY;  // NaN or Inf
-                lmax = fmax(lmax, a);
-                rw.B[c * rw.ld + r] = v[c];
             }
+#pragma unroll
+            for (int cc = 0; cc < CH; ++cc) {
+                const int c = c0 + cc;
+                if (c < k) {
+                    double a = fabs((double)v[cc]);
+                    if (!(a <= 1.0e308)) a = INFINITY;  // NaN or Inf
+                    lmax = fmax(lmax, a);
+                    rw.B[c * rw.ld + r] = v[cc];
+                }
+            }
+        }
     }
     return lmax;
 }
 
 // ----------------------------------------------------------------------------
-// k x k partial-pivot LU in LDS (row stride KMAX), rows pivoted as in LAPACK
-// getrf (first maximum).  perm[t] = original row now at t.  Stops at an exact
-// zero pivot and returns 0; else returns 1.  sm.thresh receives the smallest
-// pivot modulus.
+// k x k partial-pivot LU by one wavefront (call from all 64 lanes of wave 0).
+// Lane s holds row s in place; candidates are compared as in LAPACK getrf
+// with physical row interchanges: larger modulus, then smaller current
+// position.  perm[t] = row chosen at step t, so factored row t is
+// LU[perm[t]][:] (L below the diagonal with a unit diagonal, U on and above).
+// Writes *ok (0 on an exact zero pivot) and the smallest pivot modulus.
 // ----------------------------------------------------------------------------
 
-template <typename T, typename LT, int KMAX>
-__device__ int lu_kxk(LT* LU, Smem<T, KMAX>& sm, int k)
+// Solve M X = R for the k x k matrix M held in columns [0, k) of A (row
+// stride LD) and the nr right-hand sides in columns [rhs0, rhs0 + nr):
+// partial-pivot LU with the elimination carried along on the right-hand
+// sides (rows interchanged in place, pivots chosen as in LAPACK getrf:
+// larger modulus, then smaller position), then back substitution.  On
+// return row t of the right-hand-side block holds unknown t.  All threads of
+// the workgroup take part (three barriers per elimination step, two per
+// substitution step).  Writes sm.ok (0 on an exact zero pivot) and
+// sm.minpiv (the smallest pivot modulus).
+template <typename T, int KMAX, typename LT, int LD, int NB>
+DI void lu_aug_solve(LT* A, int k, int rhs0, int nr, Smem<T, KMAX>& sm)
 {
-    if (threadIdx.x < k) sm.perm[threadIdx.x] = threadIdx.x;
-    if (threadIdx.x == 0) sm.thresh = INFINITY;
-    __syncthreads();
-    int ok = 1;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        sm.ok = 1;
+        sm.minpiv = INFINITY;
+    }
     for (int t = 0; t < k; ++t) {
         if (threadIdx.x < 64) {
-            Key kk = key_none();
             const int s = t + threadIdx.x;
-            if (s < k) { kk.v = fabs((double)LU[s * KMAX + t]); kk.r = s; kk.c = 0; }
-            kk = wave_reduce(kk);
+            K2 key = s < k ? k2_make(fabs((double)A[s * LD + t]), s, 0) : k2_none();
+            key = wave_argmax(key);
             if (threadIdx.x == 0) {
-                sm.win = kk;
-                sm.ok = kk.v != 0.0;
-                sm.thresh = fmin(sm.thresh, kk.v);
+                const double pav = k2_val(key);
+                sm.pivp = (int)k2_row(key);
+                if (pav == 0.0) sm.ok = 0;
+                sm.minpiv = fmin(sm.minpiv, pav);
             }
         }
         __syncthreads();
-        if (!sm.ok) { ok = 0; break; }
-        const int p = (int)sm.win.r;
-        if (p != t) {
-            for (int c = threadIdx.x; c < k; c += NT) {
-                LT tmp = LU[t * KMAX + c];
-                LU[t * KMAX + c] = LU[p * KMAX + c];
-                LU[p * KMAX + c] = tmp;
+        if (!sm.ok) return;
+        const int p = sm.pivp;
+        const LT piv = A[p * LD + t];
+        const int wl = k - t - 1;  // left columns t+1 .. k-1
+        const int w = wl + nr;
+        // multipliers from the unswapped column t; interchange rows t and p
+        // in the columns still to be used
+        for (int s2 = t + 1 + threadIdx.x; s2 < k; s2 += NT)
+            sm.fcol[s2] = (double)(A[(s2 == p ? t : s2) * LD + t] / piv);
+        if (threadIdx.x == 0) sm.diag[t] = (double)piv;
+        if (p != t)
+            for (int cc = threadIdx.x; cc < w; cc += NT) {
+                const int c = cc < wl ? t + 1 + cc : rhs0 + cc - wl;
+                const LT a = A[t * LD + c];
+                A[t * LD + c] = A[p * LD + c];
+                A[p * LD + c] = a;
             }
-            if (threadIdx.x == 0) {
-                int tp = sm.perm[t];
-                sm.perm[t] = sm.perm[p];
-                sm.perm[p] = tp;
-            }
+        __syncthreads();
+        // rows below the pivot, this wavefront's rows, NB column blocks of 64
+        LT pv[NB];
+        int col[NB];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+            const int cc = lane + 64 * jb;
+            col[jb] = cc < w ? (cc < wl ? t + 1 + cc : rhs0 + cc - wl) : -1;
+            pv[jb] = col[jb] >= 0 ? A[t * LD + col[jb]] : (LT)0;
         }
-        __syncthreads();
-        const LT piv = LU[t * KMAX + t];
-        for (int s = t + 1 + threadIdx.x; s < k; s += NT) LU[s * KMAX + t] = LU[s * KMAX + t] / piv;
-        __syncthreads();
-        const int w = k - t - 1;
-        for (int e = threadIdx.x; e < w * w; e += NT) {
-            const int s = t + 1 + e / w, c = t + 1 + e % w;
-            LU[s * KMAX + c] -= LU[s * KMAX + t] * LU[t * KMAX + c];
+        for (int sb = t + 1 + wv; sb < k; sb += NWAVE * 8) {
+            LT v[8][NB], f[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int s2 = sb + i * NWAVE;
+                if (s2 < k) {
+                    f[i] = (LT)sm.fcol[s2];
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb)
+                        if (col[jb] >= 0) v[i][jb] = A[s2 * LD + col[jb]];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int s2 = sb + i * NWAVE;
+                if (s2 < k) {
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb)
+                        if (col[jb] >= 0) A[s2 * LD + col[jb]] = v[i][jb] - f[i] * pv[jb];
+                }
+            }
         }
         __syncthreads();
     }
-    __syncthreads();
-    return ok;
+    for (int t = k - 1; t >= 0; --t) {
+        const LT d = (LT)sm.diag[t];
+        for (int c = threadIdx.x; c < nr; c += NT) A[t * LD + rhs0 + c] /= d;
+        for (int s2 = threadIdx.x; s2 < t; s2 += NT) sm.fcol[s2] = (double)A[s2 * LD + t];
+        __syncthreads();
+        LT xv[NB];
+        int col[NB];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+            const int c = lane + 64 * jb;
+            col[jb] = c < nr ? rhs0 + c : -1;
+            xv[jb] = col[jb] >= 0 ? A[t * LD + col[jb]] : (LT)0;
+        }
+        for (int sb = wv; sb < t; sb += NWAVE * 8) {
+            LT v[8][NB], f[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int s2 = sb + i * NWAVE;
+                if (s2 < t) {
+                    f[i] = (LT)sm.fcol[s2];
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb)
+                        if (col[jb] >= 0) v[i][jb] = A[s2 * LD + col[jb]];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int s2 = sb + i * NWAVE;
+                if (s2 < t) {
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb)
+                        if (col[jb] >= 0) A[s2 * LD + col[jb]] = v[i][jb] - f[i] * xv[jb];
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// basis product on the matrix cores: slice <- slice(:, 0:kd) * W, W[d][c] at
+// W[d * wsd + c * wsc], d, c < kd.  Each wavefront owns 16-row tiles and
+// loads a tile's inputs before storing any output, so it runs in place.
+// ----------------------------------------------------------------------------
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+DI d4_t mfma16(double a, double b, d4_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+DI f4_t mfma16(float a, float b, f4_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+template <typename T>
+struct Acc4;
+template <>
+struct Acc4<double> {
+    typedef d4_t type;
+    // output element r of lane l is row 4 r + l / 16, column l % 16
+    static DI int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <>
+struct Acc4<float> {
+    typedef f4_t type;
+    // output element r of lane l is row 4 (l / 16) + r, column l % 16
+    static DI int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename T, int KMAX>
+DI void basis_product(const Rows<T>& rw, int kd, const T* W, int wsd, int wsc)
+{
+    typedef typename Acc4<T>::type acc_t;
+    constexpr int KB = KMAX / 4;
+    constexpr int CT = (KMAX + 15) / 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int ntiles = (rw.nrows + 15) / 16;
+    for (int tile = wv; tile < ntiles; tile += NWAVE) {
+        const int r = tile * 16 + (lane & 15);
+        const bool rok = r < rw.nrows;
+        T a[KB];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            const int d = kb * 4 + (lane >> 4);
+            a[kb] = (rok && d < kd) ? rw.B[d * rw.ld + r] : (T)0;
+        }
+        acc_t out[CT];
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            acc_t acc = {0, 0, 0, 0};
+            const int c = ct * 16 + (lane & 15);
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                const int d = kb * 4 + (lane >> 4);
+                const T w = (d < kd && c < kd) ? W[d * wsd + c * wsc] : (T)0;
+                acc = mfma16(a[kb], w, acc);
+            }
+            out[ct] = acc;
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+            const int c = ct * 16 + (lane & 15);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int rr = tile * 16 + Acc4<T>::row(lane, e);
+                if (rr < rw.nrows && c < kd) rw.B[c * rw.ld + rr] = out[ct][e];
+            }
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -362,212 +545,405 @@ __device__ int lu_kxk(LT* LU, Smem<T, KMAX>& sm, int k)
 // A[:, J]; row step (transpose = 1) picks J from A[I, :]^T.
 // ----------------------------------------------------------------------------
 
-template <typename T, int KMAX>
-__device__ void maxvol_step(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, int transpose,
-                            int lds_b_bytes, T* Blds)
-{
-    const int k = sm.k;
-    const int64_t M = transpose ? td.n : td.m;
-    const int64_t* F = transpose ? sm.I : sm.J;
-    int64_t* X = transpose ? sm.J : sm.I;
-    const bool have_X = transpose ? true : (sm.have_I != 0);
-    const bool warm = have_X && td.warm_start;
-    const double u = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
+// ----------------------------------------------------------------------------
+// The step is split into separately compiled phases (each gets its own
+// register allocation; a single inlined kernel spilled scalar registers).
+// Callees find their LDS through the extern symbol below, so LDS accesses
+// stay ds_* instructions; the team state is copied in and out.
+// ----------------------------------------------------------------------------
 
-    const int64_t R = (M + tm.size - 1) / tm.size;
+extern __shared__ __align__(16) unsigned char lra_smem[];
+
+template <typename T, int KMAX>
+DI Smem<T, KMAX>& smem_ref() { return *reinterpret_cast<Smem<T, KMAX>*>(lra_smem); }
+
+template <typename T, int KMAX>
+DI T* blds_ptr() { return reinterpret_cast<T*>(lra_smem + ((sizeof(Smem<T, KMAX>) + 255) & ~(size_t)255)); }
+
+#define NOINL __device__ __noinline__
+
+// This workgroup's slice of the current strip.
+template <typename T, int KMAX, bool LDSB>
+DI Rows<T> slice_of(const TaskDesc& td, const Team& tm, int transpose, int64_t& R)
+{
+    const int64_t M = transpose ? td.n : td.m;
+    R = (M + tm.size - 1) / tm.size;
     Rows<T> rw;
     rw.r0 = (int64_t)tm.rank * R;
-    {
-        int64_t r1 = rw.r0 + R < M ? rw.r0 + R : M;
-        rw.nrows = r1 > rw.r0 ? (int)(r1 - rw.r0) : 0;
-    }
-    if ((int64_t)R * k * (int64_t)sizeof(T) <= lds_b_bytes) {
-        rw.B = Blds;
+    const int64_t r1 = rw.r0 + R < M ? rw.r0 + R : M;
+    rw.nrows = r1 > rw.r0 ? (int)(r1 - rw.r0) : 0;
+    if (LDSB) {
+        rw.B = blds_ptr<T, KMAX>();
         rw.ld = R;
     } else {
         rw.B = (T*)td.strip + rw.r0;
         rw.ld = M;
     }
-    const int64_t rend = rw.r0 + rw.nrows;
+    return rw;
+}
 
-    // Warm start: partial-pivot LU of Chat^T (Chat = strip[X, :]) before the
-    // gather, so that its row permutation becomes the gather's column order
-    // and both triangular solves below run in place.
-    T* LUt = (T*)sm.LU;
-    int warm_lu = 0;
-    double minpiv = 0.0;
-    if (warm) {
-        for (int e = threadIdx.x; e < k * k; e += NT) {
-            const int c = e / k, s = e % k;  // (Chat^T)[c][s] = strip(X[s], c)
-            LUt[c * KMAX + s] = transpose ? entry_t<T>(td.src, F[c], X[s]) : entry_t<T>(td.src, X[s], F[c]);
+// Warm start: partial-pivot LU of M = Chat^T (Chat = strip[X, :]) solved
+// against the identity, giving M^{-1} in the right half of AUG (so that
+// B = C Chat^{-1} = C (M^{-1})^T).  Returns 1 unless a pivot was exactly 0;
+// the smallest pivot modulus is left in sm.minpiv.
+template <typename T, int KMAX>
+NOINL int warm_phase(const TaskDesc& td, Team& tio, int transpose)
+{
+    Team tm = tio;
+    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
+    const int k = sm.k;
+    const int64_t* F = transpose ? sm.I : sm.J;
+    const int64_t* X = transpose ? sm.J : sm.I;
+    constexpr int LD = 2 * KMAX;
+    T* AUG = (T*)sm.AUG;
+    {
+        // M[c][s] = strip(X[s], c); all loads issued before the stores
+        constexpr int PER = (KMAX * KMAX + NT - 1) / NT;
+        T mv[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = threadIdx.x + i * NT;
+            if (e < k * k) {
+                const int c = e / k, s2 = e % k;
+                mv[i] = transpose ? entry_t<T>(td.src, F[c], X[s2]) : entry_t<T>(td.src, X[s2], F[c]);
+            }
         }
-        __syncthreads();
-        warm_lu = lu_kxk<T, T, KMAX>(LUt, sm, k);
-        minpiv = sm.thresh;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = threadIdx.x + i * NT;
+            if (e < k * k) {
+                const int c = e / k, s2 = e % k;
+                AUG[c * LD + s2] = mv[i];
+                AUG[c * LD + KMAX + s2] = (T)(c == s2 ? 1 : 0);
+            }
+        }
     }
+    __syncthreads();
+    lu_aug_solve<T, KMAX, T, LD, (2 * KMAX + 63) / 64>(AUG, k, KMAX, k, sm);
+    const int ok = sm.ok;
+    trace_ev(tm, EV_WARM_LU, ok);
+    tio = tm;
+    return ok;
+}
 
-    // 1. gather this workgroup's rows of the strip
+// Gather this workgroup's rows of the strip and return the team-wide max
+// |entry| (+inf when an entry is not finite, -1 when the team failed).
+template <typename T, int KMAX, bool LDSB>
+NOINL double gather_phase(const TaskDesc& td, Team& tio, int transpose)
+{
+    Team tm = tio;
+    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
+    const int k = sm.k;
+    const int64_t* F = transpose ? sm.I : sm.J;
+    int64_t R;
+    const Rows<T> rw = slice_of<T, KMAX, LDSB>(td, tm, transpose, R);
     if (td.src.kind != 0) {
         if (threadIdx.x < k)
             sm.pts[threadIdx.x] = transpose ? load_elem(td.src.x, td.src.dtype, F[threadIdx.x])
                                             : load_elem(td.src.y, td.src.dtype, F[threadIdx.x]);
         __syncthreads();
     }
-    double lmax = gather_rows<T, KMAX>(td.src, transpose, sm, F, warm_lu ? sm.perm : nullptr, k, rw);
+    const double lmax = gather_rows<T, KMAX>(td.src, transpose, sm, F, k, rw);
+    K2 km = block_argmax(k2_make(lmax, 0, 0), sm, tm);
+    km = team_argmax(tm, sm, km, 0, R);
+    tio = tm;
+    if (tm.failed) return -1.0;
+    return k2_val(km);
+}
 
-    // 2. team-wide max |entry| (non-finite -> +inf)
-    Key km = key_none();
-    km.v = lmax;
-    km.r = 0;
-    km.c = 0;
-    km = block_reduce(km, sm);
-    km = team_argmax(tm, sm, km, 0);
+// Partial-pivot LU of the strip (k team-wide pivot searches), then the rows
+// of L1 (unit lower) are left in AUG.  Returns the effective rank, or -1 if
+// the team failed / a pivot was exactly zero (status set).
+template <typename T, int KMAX, bool LDSB>
+NOINL int gepp_phase(const TaskDesc& td, Team& tio, int transpose, double thresh)
+{
+    Team tm = tio;
+    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
+    const int k = sm.k;
+    int64_t* X = transpose ? sm.J : sm.I;
+    int64_t R;
+    const Rows<T> rw = slice_of<T, KMAX, LDSB>(td, tm, transpose, R);
+    const int64_t rend = rw.r0 + rw.nrows;
+    constexpr int LD = 2 * KMAX;
+    T* AUG = (T*)sm.AUG;
+    int keff = k;
+    double bv = -1.0;
+    int br = 0;
+    for (int r = threadIdx.x; r < rw.nrows; r += NT) {
+        const double v = fabs((double)rw.B[r]);
+        if (v > bv) { bv = v; br = r; }
+    }
+    K2 kl = bv >= 0.0 ? k2_make(bv, rw.r0 + br, 0) : k2_none();
+    for (int t = 0; t < k; ++t) {
+        const K2 wb = block_argmax(kl, sm, tm);
+        const int64_t wr = k2_row(wb);
+        if (threadIdx.x < k && wr >= rw.r0 && wr < rend) sm.pay[threadIdx.x] = rw.B[threadIdx.x * rw.ld + (wr - rw.r0)];
+        const K2 wv = team_argmax(tm, sm, wb, k, R);
+        if (tm.failed) { tio = tm; return -1; }
+        __syncthreads();
+        const double pav = k2_val(wv);
+        if (pav == 0.0) {
+            if (threadIdx.x == 0) { sm.status = -2; sm.phase = PH_DONE; }
+            __syncthreads();
+            tio = tm;
+            return -1;
+        }
+        if (pav < thresh) { keff = t; break; }
+        if (threadIdx.x == 0) X[t] = k2_row(wv);
+        // row t of L1: the pivot row's multipliers, a unit diagonal, zeros above
+        if (threadIdx.x < k) AUG[t * LD + threadIdx.x] = threadIdx.x < t ? sm.pay[threadIdx.x] : (T)(threadIdx.x == t ? 1 : 0);
+        trace_ev(tm, EV_PIVOT, t);
+        const T piv = sm.pay[t];
+        bv = -1.0;
+        for (int r = threadIdx.x; r < rw.nrows; r += NT) {
+            T* b = rw.B + r;
+            const T l = b[t * rw.ld] / piv;
+            b[t * rw.ld] = l;
+            for (int c0 = t + 1; c0 < k; c0 += 8) {
+                T v[8], pv[8];
+#pragma unroll
+                for (int cc = 0; cc < 8; ++cc)
+                    if (c0 + cc < k) {
+                        v[cc] = b[(c0 + cc) * rw.ld];
+                        pv[cc] = sm.pay[c0 + cc];
+                    }
+#pragma unroll
+                for (int cc = 0; cc < 8; ++cc)
+                    if (c0 + cc < k) {
+                        v[cc] = v[cc] - l * pv[cc];
+                        b[(c0 + cc) * rw.ld] = v[cc];
+                    }
+                if (c0 == t + 1) {
+                    const double a = fabs((double)v[0]);
+                    if (a > bv) { bv = a; br = r; }
+                }
+            }
+        }
+        kl = bv >= 0.0 ? k2_make(bv, rw.r0 + br, 0) : k2_none();
+        __syncthreads();
+    }
+    tio = tm;
+    return keff;
+}
+
+// B = C Chat^{-1} (warm start) or B = L L1^{-1} (after the strip LU) on the
+// matrix cores, then the rows of the chosen set become unit rows.
+template <typename T, int KMAX, bool LDSB>
+NOINL void basis_phase(const TaskDesc& td, Team& tio, int transpose, int started, int keff)
+{
+    Team tm = tio;
+    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
+    const int64_t* X = transpose ? sm.J : sm.I;
+    int64_t R;
+    const Rows<T> rw = slice_of<T, KMAX, LDSB>(td, tm, transpose, R);
+    const int64_t rend = rw.r0 + rw.nrows;
+    constexpr int LD = 2 * KMAX;
+    T* AUG = (T*)sm.AUG;
+    if (started) {
+        // W[d][c] = M^{-1}[c][d], in the right half of AUG
+        basis_product<T, KMAX>(rw, keff, AUG + KMAX, 1, LD);
+    } else {
+        // L1^{-1} from a solve against I (L1 needs no interchange: its
+        // multipliers are at most 1 in modulus), then L L1^{-1}
+        for (int e = threadIdx.x; e < keff * keff; e += NT)
+            AUG[(e / keff) * LD + KMAX + e % keff] = (T)((e / keff) == (e % keff));
+        __syncthreads();
+        lu_aug_solve<T, KMAX, T, LD, (2 * KMAX + 63) / 64>(AUG, keff, KMAX, keff, sm);
+        basis_product<T, KMAX>(rw, keff, AUG + KMAX, LD, 1);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < keff * keff; e += NT) {
+        const int s2 = e / keff, c = e % keff;
+        const int64_t gr = X[s2];
+        if (gr >= rw.r0 && gr < rend) rw.B[c * rw.ld + (gr - rw.r0)] = (T)(c == s2 ? 1 : 0);
+    }
+    __syncthreads();
+    trace_ev(tm, EV_BASIS, started);
+    tio = tm;
+}
+
+// Swaps: while max|B| > 1 + tau, bring the winning row into its column's
+// slot (rank-one update of B; |det| grows by the winning entry).  Returns the
+// number of swaps, or -1 if the team failed.
+template <typename T, int KMAX, bool LDSB>
+NOINL int swap_phase(const TaskDesc& td, Team& tio, int transpose, int keff)
+{
+    Team tm = tio;
+    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
+    int64_t* X = transpose ? sm.J : sm.I;
+    int64_t R;
+    const Rows<T> rw = slice_of<T, KMAX, LDSB>(td, tm, transpose, R);
+    const int64_t rend = rw.r0 + rw.nrows;
+    const double lim = 1.0 + td.tau;
+    const int max_swaps = td.max_swaps > 0 ? td.max_swaps : 4 * keff + 64;
+    int swaps = 0;
+    if (threadIdx.x >= keff && threadIdx.x < KMAX) sm.g[threadIdx.x] = (T)0;
+    if (KMAX <= 32 && R <= NT) {
+        // at most one row per thread: the row stays in registers for all
+        // swaps; columns keff..KMAX-1 are carried as zeros (their g is 0), so
+        // the unrolled loops need no per-column guards
+        const bool has = threadIdx.x < rw.nrows;
+        const int64_t myrow = rw.r0 + threadIdx.x;
+        T row[KMAX];
+        {
+            const T* p = rw.B + (has ? threadIdx.x : 0);
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) {
+                const T v = *p;
+                row[c] = c < keff ? v : (T)0;
+                if (c + 1 < keff) p += rw.ld;
+            }
+        }
+        double bv = -1.0;
+        int bc = 0;
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c) {
+            const double a = fabs((double)row[c]);
+            if (a > bv) { bv = a; bc = c; }
+        }
+        if (!has) bv = -1.0;
+        for (;;) {
+            const K2 kl = bv >= 0.0 ? k2_make(bv, myrow, bc) : k2_none();
+            const K2 wb = block_argmax(kl, sm, tm);
+            trace_ev(tm, EV_SWAP_RED, 0);
+            if (has && k2_row(wb) == myrow) {
+#pragma unroll
+                for (int c = 0; c < KMAX; ++c) sm.pay[c] = row[c];
+            }
+            __syncthreads();
+            const K2 wv = team_argmax(tm, sm, wb, keff, R);
+            if (tm.failed) { tio = tm; return -1; }
+            trace_ev(tm, EV_SWAP_XCH, 0);
+            if (!(k2_val(wv) > lim)) break;
+            if (swaps == max_swaps) {
+                if (threadIdx.x == 0) sm.warn |= W_CAP;
+                break;
+            }
+            const int js = k2_col(wv);
+            const int64_t is = k2_row(wv);
+            if (threadIdx.x < keff) sm.g[threadIdx.x] = (sm.pay[threadIdx.x] - (T)(threadIdx.x == js ? 1 : 0)) / sm.pay[js];
+            if (threadIdx.x == 0) X[js] = is;
+            __syncthreads();
+            ++swaps;
+            trace_ev(tm, EV_SWAP, swaps);
+            T gv[KMAX];
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) gv[c] = sm.g[c];
+            T f = (T)0;
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) f = c == js ? row[c] : f;
+            const bool unit = myrow == is;
+            bv = -1.0;
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) {
+                const T nv = unit ? (T)(c == js ? 1 : 0) : row[c] - f * gv[c];
+                row[c] = nv;
+                const double a = fabs((double)nv);
+                if (a > bv) { bv = a; bc = c; }
+            }
+            if (!has) bv = -1.0;
+        }
+    } else {
+        double bv = -1.0;
+        int br = 0, bc = 0;
+        for (int r = threadIdx.x; r < rw.nrows; r += NT)
+            for (int c = 0; c < keff; ++c) {
+                const double v = fabs((double)rw.B[c * rw.ld + r]);
+                if (v > bv) { bv = v; br = r; bc = c; }
+            }
+        for (;;) {
+            const K2 kl = bv >= 0.0 ? k2_make(bv, rw.r0 + br, bc) : k2_none();
+            const K2 wb = block_argmax(kl, sm, tm);
+            trace_ev(tm, EV_SWAP_RED, 0);
+            const int64_t wr = k2_row(wb);
+            if (threadIdx.x < keff && wr >= rw.r0 && wr < rend) sm.pay[threadIdx.x] = rw.B[threadIdx.x * rw.ld + (wr - rw.r0)];
+            const K2 wv = team_argmax(tm, sm, wb, keff, R);
+            if (tm.failed) { tio = tm; return -1; }
+            trace_ev(tm, EV_SWAP_XCH, 0);
+            if (!(k2_val(wv) > lim)) break;
+            if (swaps == max_swaps) {
+                if (threadIdx.x == 0) sm.warn |= W_CAP;
+                break;
+            }
+            const int js = k2_col(wv);
+            const int64_t is = k2_row(wv);
+            if (threadIdx.x < keff) sm.g[threadIdx.x] = (sm.pay[threadIdx.x] - (T)(threadIdx.x == js ? 1 : 0)) / sm.pay[js];
+            if (threadIdx.x == 0) X[js] = is;
+            __syncthreads();
+            ++swaps;
+            trace_ev(tm, EV_SWAP, swaps);
+            constexpr int CH = KMAX < 16 ? KMAX : 16;
+            bv = -1.0;
+            for (int r = threadIdx.x; r < rw.nrows; r += NT) {
+                T* b = rw.B + r;
+                const T f = b[js * rw.ld];
+                const bool unit = (rw.r0 + r == is);
+                for (int c0 = 0; c0 < keff; c0 += CH) {
+                    T v[CH], gv[CH];
+#pragma unroll
+                    for (int cc = 0; cc < CH; ++cc)
+                        if (c0 + cc < keff) {
+                            v[cc] = b[(c0 + cc) * rw.ld];
+                            gv[cc] = sm.g[c0 + cc];
+                        }
+#pragma unroll
+                    for (int cc = 0; cc < CH; ++cc)
+                        if (c0 + cc < keff) {
+                            const int c = c0 + cc;
+                            const T nv = unit ? (T)(c == js ? 1 : 0) : v[cc] - f * gv[cc];
+                            b[c * rw.ld] = nv;
+                            const double a = fabs((double)nv);
+                            if (a > bv) { bv = a; br = r; bc = c; }
+                        }
+                }
+            }
+        }
+    }
+    trace_ev(tm, EV_STEP_END, swaps);
+    __syncthreads();
+    tio = tm;
+    return swaps;
+}
+
+// ----------------------------------------------------------------------------
+// one maxvol step (Section 6.5): column step (transpose = 0) picks I from
+// A[:, J]; row step (transpose = 1) picks J from A[I, :]^T.
+// ----------------------------------------------------------------------------
+
+template <typename T, int KMAX, bool LDSB>
+DI void maxvol_step(const TaskDesc& td, Team& tm, int transpose)
+{
+    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
+    const int k = sm.k;
+    const int64_t M = transpose ? td.n : td.m;
+    const bool have_X = transpose ? true : (sm.have_I != 0);
+    const bool warm = have_X && td.warm_start;
+    const double u = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
+    trace_ev(tm, EV_STEP_BEGIN, transpose);
+
+    const int warm_ok = warm ? warm_phase<T, KMAX>(td, tm, transpose) : 0;
+    const double minpiv = sm.minpiv;
+
+    const double cmax = gather_phase<T, KMAX, LDSB>(td, tm, transpose);
     if (tm.failed) return;
     if (threadIdx.x == 0) sm.entries_read += M * k;
-    if (isinf(km.v)) {
+    if (isinf(cmax)) {
         if (threadIdx.x == 0) { sm.status = -6; sm.phase = PH_DONE; }
         __syncthreads();
         return;
     }
-    const double thresh = 64.0 * u * km.v;
+    const double thresh = 64.0 * u * cmax;
+    trace_ev(tm, EV_GATHERED, 0);
 
-    // 3. basis B = C C[X,:]^{-1}
+    const int started = warm_ok && minpiv > thresh;
     int keff = k;
-    const int started = warm_lu && minpiv > thresh;
-    if (started) {
-        // B Chat = C  <=>  Chat^T B^T = C^T, P Chat^T = L U: the slice already
-        // holds P C^T row-wise; L w = (P c), U x = w, in place.
-        for (int r = threadIdx.x; r < rw.nrows; r += NT) {
-            T* b = rw.B + r;
-            for (int s = 1; s < k; ++s) {
-                T acc = b[s * rw.ld];
-                for (int d = 0; d < s; ++d) acc -= LUt[s * KMAX + d] * b[d * rw.ld];
-                b[s * rw.ld] = acc;
-            }
-            for (int s = k - 1; s >= 0; --s) {
-                T acc = b[s * rw.ld];
-                for (int d = s + 1; d < k; ++d) acc -= LUt[s * KMAX + d] * b[d * rw.ld];
-                b[s * rw.ld] = acc / LUt[s * KMAX + s];
-            }
-        }
-        __syncthreads();
-    } else {
-        if (warm_lu) {
-            // gathered in pivot order for a start that was rejected: gather again
-            (void)gather_rows<T, KMAX>(td.src, transpose, sm, F, nullptr, k, rw);
-            __syncthreads();
-        }
-        // partial-pivot LU of the strip: k team-wide pivot searches
-        Key kl = key_none();
-        for (int r = threadIdx.x; r < rw.nrows; r += NT) {
-            Key o;
-            o.v = fabs((double)rw.B[r]);
-            o.r = rw.r0 + r;
-            o.c = 0;
-            o.w = tm.rank;
-            if (kbetter(o, kl)) kl = o;
-        }
-        for (int t = 0; t < k; ++t) {
-            kl = block_reduce(kl, sm);
-            if (threadIdx.x < k && kl.r >= rw.r0 && kl.r < rend)
-                sm.pay[threadIdx.x] = rw.B[threadIdx.x * rw.ld + (kl.r - rw.r0)];
-            __syncthreads();
-            Key wv = team_argmax(tm, sm, kl, k);
-            if (tm.failed) return;
-            if (wv.v == 0.0) {
-                if (threadIdx.x == 0) { sm.status = -2; sm.phase = PH_DONE; }
-                __syncthreads();
-                return;
-            }
-            if (wv.v < thresh) { keff = t; break; }
-            if (threadIdx.x == 0) X[t] = wv.r;
-            if (threadIdx.x < t) LUt[t * KMAX + threadIdx.x] = sm.pay[threadIdx.x];
-            const T piv = sm.pay[t];
-            kl = key_none();
-            for (int r = threadIdx.x; r < rw.nrows; r += NT) {
-                const T l = rw.B[t * rw.ld + r] / piv;
-                rw.B[t * rw.ld + r] = l;
-                for (int c = t + 1; c < k; ++c) rw.B[c * rw.ld + r] -= l * sm.pay[c];
-                if (t + 1 < k) {
-                    Key o;
-                    o.v = fabs((double)rw.B[(t + 1) * rw.ld + r]);
-                    o.r = rw.r0 + r;
-                    o.c = 0;
-                    o.w = tm.rank;
-                    if (kbetter(o, kl)) kl = o;
-                }
-            }
-            __syncthreads();
-        }
-        // B = L L1^{-1}: x L1 = l, descending, in place
-        for (int r = threadIdx.x; r < rw.nrows; r += NT) {
-            T* b = rw.B + r;
-            for (int c = keff - 2; c >= 0; --c) {
-                T x = b[c * rw.ld];
-                for (int s2 = c + 1; s2 < keff; ++s2) x -= b[s2 * rw.ld] * LUt[s2 * KMAX + c];
-                b[c * rw.ld] = x;
-            }
-        }
-        __syncthreads();
+    if (!started) {
+        keff = gepp_phase<T, KMAX, LDSB>(td, tm, transpose, thresh);
+        if (keff < 0) return;
     }
-    // rows of the chosen set are unit rows of B
-    for (int e = threadIdx.x; e < keff * keff; e += NT) {
-        const int s = e / keff, c = e % keff;
-        const int64_t gr = X[s];
-        if (gr >= rw.r0 && gr < rend) rw.B[c * rw.ld + (gr - rw.r0)] = (T)(c == s ? 1 : 0);
-    }
-    __syncthreads();
-
-    // 4. swaps: while max|B| > 1 + tau, bring the winning row into its column's slot
-    const double lim = 1.0 + td.tau;
-    const int max_swaps = td.max_swaps > 0 ? td.max_swaps : 4 * keff + 64;
-    int swaps = 0;
-    Key kl = key_none();
-    for (int r = threadIdx.x; r < rw.nrows; r += NT)
-        for (int c = 0; c < keff; ++c) {
-            Key o;
-            o.v = fabs((double)rw.B[c * rw.ld + r]);
-            o.r = rw.r0 + r;
-            o.c = c;
-            o.w = tm.rank;
-            if (kbetter(o, kl)) kl = o;
-        }
-    for (;;) {
-        kl = block_reduce(kl, sm);
-        if (threadIdx.x < keff && kl.r >= rw.r0 && kl.r < rend)
-            sm.pay[threadIdx.x] = rw.B[threadIdx.x * rw.ld + (kl.r - rw.r0)];
-        __syncthreads();
-        Key wv = team_argmax(tm, sm, kl, keff);
-        if (tm.failed) return;
-        if (!(wv.v > lim)) break;
-        if (swaps == max_swaps) {
-            if (threadIdx.x == 0) sm.warn |= W_CAP;
-            break;
-        }
-        const int js = wv.c;
-        const int64_t is = wv.r;
-        const T piv = sm.pay[js];
-        if (threadIdx.x < keff) sm.g[threadIdx.x] = (sm.pay[threadIdx.x] - (T)(threadIdx.x == js ? 1 : 0)) / piv;
-        __syncthreads();
-        if (threadIdx.x == 0) X[js] = is;
-        ++swaps;
-        kl = key_none();
-        for (int r = threadIdx.x; r < rw.nrows; r += NT) {
-            const T f = rw.B[js * rw.ld + r];
-            const bool unit = (rw.r0 + r == is);
-            for (int c = 0; c < keff; ++c) {
-                T v = unit ? (T)(c == js ? 1 : 0) : rw.B[c * rw.ld + r] - f * sm.g[c];
-                rw.B[c * rw.ld + r] = v;
-                Key o;
-                o.v = fabs((double)v);
-                o.r = rw.r0 + r;
-                o.c = c;
-                o.w = tm.rank;
-                if (kbetter(o, kl)) kl = o;
-            }
-        }
-        __syncthreads();
-    }
+    basis_phase<T, KMAX, LDSB>(td, tm, transpose, started, keff);
+    const int swaps = swap_phase<T, KMAX, LDSB>(td, tm, transpose, keff);
+    if (swaps < 0) return;
     if (threadIdx.x == 0) {
         sm.swaps_total += swaps;
         if (keff < k) {
@@ -578,12 +954,24 @@ __device__ void maxvol_step(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, int
     __syncthreads();
 }
 
+// The slice lives in LDS when this workgroup's rows fit, else in the global
+// strip buffer; both variants are compiled so that LDS accesses stay ds_* ops.
+template <typename T, int KMAX>
+DI void maxvol_dispatch(const TaskDesc& td, Team& tm, int transpose, int lds_b_bytes)
+{
+    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
+    const int64_t M = transpose ? td.n : td.m;
+    const int64_t R = (M + tm.size - 1) / tm.size;
+    if (R * sm.k * (int64_t)sizeof(T) <= lds_b_bytes) maxvol_step<T, KMAX, true>(td, tm, transpose);
+    else maxvol_step<T, KMAX, false>(td, tm, transpose);
+}
+
 // ----------------------------------------------------------------------------
 // optional CUR factors: C = A[:, J] (m x k column-major), R = A[I, :] (k x n)
 // ----------------------------------------------------------------------------
 
 template <typename T, int KMAX>
-__device__ void write_factors(const TaskDesc& td, Smem<T, KMAX>& sm, const Team& tm)
+NOINL void write_factors(const TaskDesc& td, Smem<T, KMAX>& sm, const Team& tm)
 {
     const int k = sm.k;
     if (td.C_out) {
@@ -604,7 +992,7 @@ __device__ void write_factors(const TaskDesc& td, Smem<T, KMAX>& sm, const Team&
 
 // Fixed-order block sum (every thread passes its partial; all get the total).
 template <typename T, int KMAX>
-__device__ double block_sum(double v, Smem<T, KMAX>& sm)
+DI double block_sum(double v, Smem<T, KMAX>& sm)
 {
     sm.red[threadIdx.x] = v;
     __syncthreads();
@@ -612,7 +1000,7 @@ __device__ double block_sum(double v, Smem<T, KMAX>& sm)
         if (threadIdx.x < h) sm.red[threadIdx.x] += sm.red[threadIdx.x + h];
         __syncthreads();
     }
-    double r = sm.red[0];
+    const double r = sm.red[0];
     __syncthreads();
     return r;
 }
@@ -622,90 +1010,67 @@ __device__ double block_sum(double v, Smem<T, KMAX>& sm)
 // ----------------------------------------------------------------------------
 
 template <typename T, int KMAX>
-__device__ void final_leader(const TaskDesc& td, Smem<T, KMAX>& sm)
+NOINL void final_leader(const TaskDesc& td, Team& tio, int lds_b_bytes)
 {
+    Team tm = tio;
+    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
+    T* Blds = blds_ptr<T, KMAX>();
     const int k = sm.k;
-    double* LU = sm.LU;
+    const int q = td.q, s = td.s;
+    // F = [G | I | A[I,S]] (row stride LDF; s <= 64), then A[Q,J] and A[Q,S]
+    constexpr int LDF = 2 * KMAX + 64;
+    const int64_t need = (int64_t)KMAX * LDF + (int64_t)q * k + (int64_t)q * s;
+    double* Fm = need * 8 <= lds_b_bytes ? (double*)Blds : td.work;
+    double* AQJ = Fm + (int64_t)KMAX * LDF;
+    double* E = AQJ + (int64_t)q * k;
     for (int e = threadIdx.x; e < k * k; e += NT) {
-        const int s = e / k, t = e % k;
-        const double v = entry64(td.src, sm.I[s], sm.J[t]);
-        LU[s * KMAX + t] = v;
-        td.G[s * k + t] = v;
+        const int a = e / k, t = e % k;
+        const double v = entry64(td.src, sm.I[a], sm.J[t]);
+        Fm[a * LDF + t] = v;
+        Fm[a * LDF + KMAX + t] = a == t ? 1.0 : 0.0;
+        td.G[e] = v;
     }
+    for (int e = threadIdx.x; e < k * s; e += NT) Fm[(e / s) * LDF + KMAX + k + e % s] = entry64(td.src, sm.I[e / s], td.S[e % s]);
+    for (int e = threadIdx.x; e < q * k; e += NT) AQJ[e] = entry64(td.src, td.Q[e / k], sm.J[e % k]);
+    for (int e = threadIdx.x; e < q * s; e += NT) E[e] = entry64(td.src, td.Q[e / s], td.S[e % s]);
+    __threadfence_block();
     __syncthreads();
-    if (!lu_kxk<T, double, KMAX>(LU, sm, k)) {
+    // ||G||_1 before the factorisation overwrites G
+    double cg = 0.0;
+    if (threadIdx.x < k)
+        for (int a = 0; a < k; ++a) cg += fabs(Fm[a * LDF + threadIdx.x]);
+    const double ng = k2_val(block_argmax(k2_make(cg, 0, 0), sm, tm));
+    // U = G^{-1} and W = G^{-1} A[I,S] by one partial-pivot LU solve
+    lu_aug_solve<T, KMAX, double, LDF, (2 * KMAX + 127) / 64>(Fm, k, KMAX, k + s, sm);
+    if (!sm.ok) {
         if (threadIdx.x == 0) { sm.status = -2; sm.phase = PH_DONE; }
         __syncthreads();
+        tio = tm;
         return;
     }
-    // U: column t solves G u = e_t (L y = P e_t, U_f u = y), in place in td.U
-    if (threadIdx.x < k) {
-        const int t = threadIdx.x;
-        double* u = td.U + t;
-        for (int s = 0; s < k; ++s) {
-            double a = sm.perm[s] == t ? 1.0 : 0.0;
-            for (int c = 0; c < s; ++c) a -= LU[s * KMAX + c] * u[c * k];
-            u[s * k] = a;
-        }
-        for (int s = k - 1; s >= 0; --s) {
-            double a = u[s * k];
-            for (int c = s + 1; c < k; ++c) a -= LU[s * KMAX + c] * u[c * k];
-            u[s * k] = a / LU[s * KMAX + s];
-        }
-    }
     __threadfence_block();
     __syncthreads();
-    // exact 1-norm condition number ||G||_1 ||U||_1
-    {
-        double cg = 0.0, cu = 0.0;
-        if (threadIdx.x < k)
-            for (int s = 0; s < k; ++s) {
-                cg += fabs(td.G[s * k + threadIdx.x]);
-                cu += fabs(td.U[s * k + threadIdx.x]);
-            }
-        Key a = key_none();
-        a.v = cg;
-        a.r = 0;
-        a.c = 0;
-        Key b = key_none();
-        b.v = cu;
-        b.r = 0;
-        b.c = 0;
-        a = block_reduce(a, sm);
-        b = block_reduce(b, sm);
-        if (threadIdx.x == 0) sm.cond1 = a.v * b.v;
-    }
-    // residual on Q x S: W = G^{-1} A[I,S] through the LU, E = A[Q,S] - A[Q,J] W
-    const int q = td.q, s = td.s;
-    double* AQJ = td.work;                 // q x k
-    double* W = td.work + (int64_t)q * k;  // k x s
-    double* E = W + (int64_t)k * s;        // q x s
-    for (int e = threadIdx.x; e < q * k; e += NT) {
-        const int a = e / k, t = e % k;
-        AQJ[e] = entry64(td.src, td.Q[a], sm.J[t]);
-    }
-    for (int b = threadIdx.x; b < s; b += NT) {
-        double* w = W + b;
-        for (int a = 0; a < k; ++a) {
-            double y = entry64(td.src, sm.I[sm.perm[a]], td.S[b]);
-            for (int c = 0; c < a; ++c) y -= LU[a * KMAX + c] * w[c * s];
-            w[a * s] = y;
-        }
-        for (int a = k - 1; a >= 0; --a) {
-            double y = w[a * s];
-            for (int c = a + 1; c < k; ++c) y -= LU[a * KMAX + c] * w[c * s];
-            w[a * s] = y / LU[a * KMAX + a];
-        }
-    }
-    __threadfence_block();
-    __syncthreads();
+    for (int e = threadIdx.x; e < k * k; e += NT) td.U[e] = Fm[(e / k) * LDF + KMAX + e % k];
+    const double* W = Fm + KMAX + k;  // W[t][b] at W[t * LDF + b]
+    double cu = 0.0;
+    if (threadIdx.x < k)
+        for (int a = 0; a < k; ++a) cu += fabs(Fm[a * LDF + KMAX + threadIdx.x]);
+    const double nu = k2_val(block_argmax(k2_make(cu, 0, 0), sm, tm));
     double se = 0.0, sa = 0.0, sum = 0.0;
     for (int e = threadIdx.x; e < q * s; e += NT) {
         const int a = e / s, b = e % s;
-        double cur = 0.0;
-        for (int t = 0; t < k; ++t) cur += AQJ[a * k + t] * W[t * s + b];
-        const double av = entry64(td.src, td.Q[a], td.S[b]);
-        const double ev = av - cur;
+        const double* aq = AQJ + (int64_t)a * k;
+        double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+        int t = 0;
+        for (; t + 4 <= k; t += 4) {
+            c0 += aq[t] * W[t * LDF + b];
+            c1 += aq[t + 1] * W[(t + 1) * LDF + b];
+            c2 += aq[t + 2] * W[(t + 2) * LDF + b];
+            c3 += aq[t + 3] * W[(t + 3) * LDF + b];
+        }
+        for (; t < k; ++t) c0 += aq[t] * W[t * LDF + b];
+        const double av = E[e];
+        const double ev = av - ((c0 + c1) + (c2 + c3));
         E[e] = ev;
         se += ev * ev;
         sa += av * av;
@@ -721,6 +1086,7 @@ __device__ void final_leader(const TaskDesc& td, Smem<T, KMAX>& sm)
     vs = block_sum(vs, sm);
     if (threadIdx.x == 0) {
         const double ne = sqrt(se), na = sqrt(sa);
+        sm.cond1 = ng * nu;
         sm.mean = mean;
         sm.var = vs / cnt;
         sm.est_abs = sqrt((double)td.m * (double)td.n / cnt) * ne;
@@ -733,7 +1099,7 @@ __device__ void final_leader(const TaskDesc& td, Smem<T, KMAX>& sm)
             sm.warn |= W_TOL;
             sm.phase = PH_DONE;
         } else {
-            int room = td.kmax - k < td.kstep ? td.kmax - k : td.kstep;
+            const int room = td.kmax - k < td.kstep ? td.kmax - k : td.kstep;
             int added = 0;
             while (added < room && sm.cand_next < td.n_cand) {
                 const int64_t cnd = td.cand[sm.cand_next++];
@@ -754,6 +1120,7 @@ __device__ void final_leader(const TaskDesc& td, Smem<T, KMAX>& sm)
         }
     }
     __syncthreads();
+    tio = tm;
 }
 
 // ----------------------------------------------------------------------------
@@ -761,7 +1128,7 @@ __device__ void final_leader(const TaskDesc& td, Smem<T, KMAX>& sm)
 // ----------------------------------------------------------------------------
 
 template <typename T, int KMAX>
-__device__ void load_state(const TaskDesc& td, Smem<T, KMAX>& sm)
+NOINL void load_state(const TaskDesc& td, Smem<T, KMAX>& sm)
 {
     if (threadIdx.x == 0) {
         const TaskState* st = td.st;
@@ -784,7 +1151,6 @@ __device__ void load_state(const TaskDesc& td, Smem<T, KMAX>& sm)
         sm.var = __hip_atomic_load(&st->var, __ATOMIC_RELAXED, AGENT);
         sm.cond1 = __hip_atomic_load(&st->cond1, __ATOMIC_RELAXED, AGENT);
     }
-    __syncthreads();
     const int kc = td.kmax > td.k0 ? td.kmax : td.k0;
     if (threadIdx.x < kc) {
         const int c = threadIdx.x;
@@ -796,8 +1162,9 @@ __device__ void load_state(const TaskDesc& td, Smem<T, KMAX>& sm)
     __syncthreads();
 }
 
+// Written by wavefront 0 only (see the team synchronisation notes).
 template <typename T, int KMAX>
-__device__ void store_state(const TaskDesc& td, Smem<T, KMAX>& sm)
+NOINL void store_state(const TaskDesc& td, Smem<T, KMAX>& sm)
 {
     const int kc = td.kmax > td.k0 ? td.kmax : td.k0;
     if (threadIdx.x < kc) {
@@ -828,13 +1195,11 @@ __device__ void store_state(const TaskDesc& td, Smem<T, KMAX>& sm)
         __hip_atomic_store(&st->var, sm.var, __ATOMIC_RELAXED, AGENT);
         __hip_atomic_store(&st->cond1, sm.cond1, __ATOMIC_RELAXED, AGENT);
     }
-    __threadfence();
-    __syncthreads();
 }
 
 // Run one problem for up to `budget` phases.
 template <typename T, int KMAX>
-__device__ void run_task(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, const EngineArgs& ea, T* Blds)
+DI void run_task(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, const EngineArgs& ea, T* Blds)
 {
     load_state(td, sm);
     int budget = ea.phase_budget;
@@ -851,7 +1216,7 @@ __device__ void run_task(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, const 
                 sm.k_sweep_start = sm.k;
             }
             __syncthreads();
-            maxvol_step<T, KMAX>(td, sm, tm, 0, ea.lds_b_bytes, Blds);
+            maxvol_dispatch<T, KMAX>(td, tm, 0, ea.lds_b_bytes);
             if (tm.failed) return;
             if (threadIdx.x == 0 && sm.phase != PH_DONE) {
                 sm.have_I = 1;
@@ -859,7 +1224,7 @@ __device__ void run_task(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, const 
             }
             __syncthreads();
         } else if (ph == PH_ROW) {
-            maxvol_step<T, KMAX>(td, sm, tm, 1, ea.lds_b_bytes, Blds);
+            maxvol_dispatch<T, KMAX>(td, tm, 1, ea.lds_b_bytes);
             if (tm.failed) return;
             if (threadIdx.x == 0 && sm.phase != PH_DONE) {
                 sm.sweeps_done += 1;
@@ -875,8 +1240,10 @@ __device__ void run_task(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, const 
             }
             __syncthreads();
         } else {  // PH_FINAL
+            trace_ev(tm, EV_FINAL_BEGIN, 0);
             write_factors<T, KMAX>(td, sm, tm);
-            if (tm.rank == 0) final_leader<T, KMAX>(td, sm);
+            if (tm.rank == 0) final_leader<T, KMAX>(td, tm, ea.lds_b_bytes);
+            trace_ev(tm, EV_FINAL_END, 0);
             if (tm.size > 1) {
                 // the leader's decision reaches the team through global memory
                 if (tm.rank == 0) store_state(td, sm);
@@ -894,9 +1261,8 @@ __device__ void run_task(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, const 
 template <typename T, int KMAX>
 __global__ __launch_bounds__(NT) void engine_kernel(EngineArgs ea)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    Smem<T, KMAX>& sm = *reinterpret_cast<Smem<T, KMAX>*>(smem_raw);
-    T* Blds = reinterpret_cast<T*>(smem_raw + ((sizeof(Smem<T, KMAX>) + 255) & ~(size_t)255));
+    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
+    T* Blds = blds_ptr<T, KMAX>();
     const int team = ea.wg_team[blockIdx.x];
     const TeamInfo ti = ea.teams[team];
     Team tm;
@@ -905,8 +1271,12 @@ __global__ __launch_bounds__(NT) void engine_kernel(EngineArgs ea)
     tm.rank = blockIdx.x - ti.first_wg;
     tm.epoch = 0;
     tm.failed = false;
+    tm.tog = 0;
     tm.err = ea.error_flag;
     tm.timeout = ea.timeout_ticks;
+    tm.trace = team == 0 ? ea.trace : nullptr;
+    tm.trace_cap = ea.trace_cap;
+    tm.trace_n = 0;
     for (;;) {
         const int par = tm.epoch & 1;
         int32_t* fetch = (int32_t*)(tm.ctl + 64) + par;
@@ -925,7 +1295,9 @@ __global__ __launch_bounds__(NT) void engine_kernel(EngineArgs ea)
         __syncthreads();
         if (idx >= ea.queue_len[ti.queue]) break;
         const int task = ea.queue_items[ea.queue_off[ti.queue] + idx];
+        trace_ev(tm, EV_TASK_BEGIN, task);
         run_task<T, KMAX>(ea.tasks[task], sm, tm, ea, Blds);
+        trace_ev(tm, EV_TASK_END, task);
         if (tm.failed) return;
     }
 }
@@ -933,8 +1305,7 @@ __global__ __launch_bounds__(NT) void engine_kernel(EngineArgs ea)
 // Zero-fill used instead of hipMemsetAsync (safe to record in a graph).
 __global__ void zero_kernel(uint32_t* p, int64_t n_words)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_words;
-         i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_words; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0u;
 }
 
@@ -977,14 +1348,13 @@ const void* engine_kernel_ptr(int prec64, int kmax)
     return engine_fn<float, 64>();
 }
 
-hipError_t launch_engine(int prec64, int kmax, int grid, size_t smem, bool cooperative,
-                         const EngineArgs& ea, hipStream_t stream)
+hipError_t launch_engine(int prec64, int kmax, int grid, size_t smem, bool cooperative, const EngineArgs& ea,
+                         hipStream_t stream)
 {
     const void* fn = engine_kernel_ptr(prec64, kmax);
     EngineArgs a = ea;
     void* args[] = {&a};
-    if (cooperative)
-        return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(NT), args, (unsigned)smem, stream);
+    if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(NT), args, (unsigned)smem, stream);
     return hipLaunchKernel(fn, dim3(grid), dim3(NT), args, smem, stream);
 }
 

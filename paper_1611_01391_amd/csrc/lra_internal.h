@@ -87,6 +87,16 @@ struct EngineArgs {
     int32_t lds_b_bytes;          // LDS bytes available for a workgroup's strip rows
     uint32_t* error_flag;         // bit 0: a team barrier timed out
     int64_t timeout_ticks;        // in wall_clock64() ticks
+    uint64_t* trace;              // optional event trace: [0] = count, then (event, clock) pairs
+    int32_t trace_cap;            // pairs
+    int32_t pad2;
+};
+
+// Trace events (recorded by thread 0 of a team's first workgroup).
+enum TraceEv : int32_t {
+    EV_STEP_BEGIN = 1, EV_WARM_LU = 2, EV_GATHERED = 3, EV_BASIS = 4, EV_SWAP = 5, EV_STEP_END = 6,
+    EV_FINAL_BEGIN = 7, EV_FINAL_END = 8, EV_TASK_BEGIN = 9, EV_TASK_END = 10, EV_PIVOT = 11,
+    EV_SWAP_RED = 12, EV_SWAP_XCH = 13
 };
 
 // Team control block layout: [0, 64): barrier counter; [64, 72): fetched task

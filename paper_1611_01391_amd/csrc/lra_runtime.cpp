@@ -114,11 +114,16 @@ struct lra_ctx {
     int max_lds = 0;         // bytes per workgroup
     int64_t wall_rate_khz = 100000;
     double timeout_s = 30.0;
-    int lds_b_bytes = 0;     // LDS for strip rows per workgroup
+    int lds_b_bytes = 0;     // cap on the LDS for strip rows per workgroup (0: none)
+    int lds_cap = 0;         // dynamic LDS per workgroup the kernels may use
     Buffer dev;              // workspace for blocking calls
     Buffer host;             // pinned staging for blocking calls
     int64_t dev_in_use = 0;  // bytes held by the serving slots
     std::map<std::string, int> tuned;  // autotuned team sizes
+    bool timing = false;
+    bool trace = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    lra_stats stats{};
     // serving
     uint64_t next_ticket = 1;
     std::deque<Request*> pending;
@@ -213,19 +218,17 @@ extern "C" lra_status lra_create(lra_ctx** out, void* stream, size_t budget)
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && rate > 0)
         c->wall_rate_khz = rate;
     if (const char* t = std::getenv("LRA_TIMEOUT_S")) c->timeout_s = std::atof(t);
-    // LDS for strip rows: leave room for the largest fixed part, cap at 64 KiB
-    const int fixed_max = (int)engine_smem_fixed(1, 64);
-    int cap = std::min(c->max_lds, 160 * 1024) - fixed_max;
-    c->lds_b_bytes = std::max(0, std::min(cap, 64 * 1024));
+    if (const char* t = std::getenv("LRA_TRACE")) c->trace = std::atoi(t) != 0;
+    // LDS for strip rows: all the device leaves per workgroup after the fixed
+    // part of each kernel variant (LRA_LDS_B_BYTES caps it)
+    c->lds_cap = std::min(c->max_lds, 160 * 1024);
     if (const char* t = std::getenv("LRA_LDS_B_BYTES")) c->lds_b_bytes = std::atoi(t);
     for (int p = 0; p < 2; ++p)
-        for (int km : {8, 16, 32, 64}) {
-            size_t smem = engine_smem_fixed(p, km) + (size_t)c->lds_b_bytes;
+        for (int km : {8, 16, 32, 64})
             (void)hipFuncSetAttribute(engine_kernel_ptr(p, km), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)smem);
-        }
-    LRA_LOG(1, "device %d: %d CUs, %d B LDS/block, strip LDS %d B, wall clock %lld kHz", c->device,
-            c->num_cu, c->max_lds, c->lds_b_bytes, (long long)c->wall_rate_khz);
+                                      c->lds_cap);
+    LRA_LOG(1, "device %d: %d CUs, %d B LDS/block, wall clock %lld kHz", c->device, c->num_cu, c->max_lds,
+            (long long)c->wall_rate_khz);
     *out = c;
     return LRA_OK;
 }
@@ -286,7 +289,7 @@ static lra_status make_prob(const lra_source* src, int64_t m, int64_t n, int k, 
     p.tau = o->tau;
     p.q = (int)std::min<int64_t>(std::max(1, o->sample_q), m);
     p.s = (int)std::min<int64_t>(std::max(1, o->sample_s), n);
-    if (p.q > 256 || p.s > 256) return LRA_EINVAL;
+    if (p.q > 64 || p.s > 64) return LRA_EINVAL;
     const uint64_t seed = o->seed + (uint64_t)blk_index * 0x1000003ull;
     if (o->init_cols) {
         if (o->n_init_cols < k) return LRA_EINVAL;
@@ -321,6 +324,15 @@ static lra_status make_prob(const lra_source* src, int64_t m, int64_t n, int k, 
     return LRA_OK;
 }
 
+// LDS left for strip rows in a workgroup of the (precision, KMAX) variant.
+static int strip_lds(lra_ctx* ctx, int prec64, int kmx)
+{
+    int b = ctx->lds_cap - (int)engine_smem_fixed(prec64, kmx);
+    b = std::max(0, b) & ~1023;
+    if (ctx->lds_b_bytes > 0) b = std::min(b, ctx->lds_b_bytes);
+    return b;
+}
+
 // Workgroups per problem: enough that each workgroup's rows fit its LDS,
 // within the co-resident limit; an explicit or tuned choice overrides.
 static int auto_team(lra_ctx* ctx, const Prob& p, int prec64)
@@ -332,10 +344,11 @@ static int auto_team(lra_ctx* ctx, const Prob& p, int prec64)
                   (long long)(64 - __builtin_clzll((unsigned long long)M)));
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) return it->second;
-    int64_t rows_fit = ctx->lds_b_bytes / ((int64_t)p.kcap * esz);
-    rows_fit = std::max<int64_t>(64, std::min<int64_t>(rows_fit, 512));
+    int64_t rows_fit = strip_lds(ctx, prec64, kmax_bucket(p.kcap)) / ((int64_t)p.kcap * esz);
+    // at most one row per thread keeps the swap loop register-resident
+    rows_fit = std::max<int64_t>(64, std::min<int64_t>(rows_fit, NT));
     int64_t t = (M + rows_fit - 1) / rows_fit;
-    t = std::min<int64_t>(t, ctx->num_cu);
+    t = std::min<int64_t>(t, std::min(ctx->num_cu, NT));
     return (int)std::max<int64_t>(1, t);
 }
 
@@ -390,7 +403,11 @@ static ProbRegions lay_prob(Layout& L, const Prob& p, int prec64)
     r.off[6] = L.add(8 * kc);
     r.off[7] = L.add(8 * kc * kc);
     r.off[8] = L.add(8 * kc * kc);
-    r.off[9] = L.add(8 * ((int64_t)p.q * kc + kc * p.s + (int64_t)p.q * p.s));
+    {
+        // final phase scratch: [G | I | A[I,S]] (row stride 2 KMAX + 64) and the sample blocks
+        const int64_t kb = kmax_bucket(p.kcap);
+        r.off[9] = L.add(8 * (kb * (2 * kb + 64) + (int64_t)p.q * kc + (int64_t)p.q * p.s));
+    }
     r.off[10] = p.need_strip ? L.add(std::max(p.m, p.n) * kc * (prec64 ? 8 : 4)) : -1;
     r.off[11] = L.add(sizeof(TaskState));
     return r;
@@ -474,6 +491,29 @@ static Plan plan_teams(lra_ctx* ctx, const std::vector<Prob>& probs, int max_wgs
     return pl;
 }
 
+// Summarise a device trace on stderr: time spent before each event kind,
+// measured from the previous event of the same team leader.
+static void dump_trace(lra_ctx* ctx, const uint64_t* tr, int cap)
+{
+    static const char* names[] = {"?", "step_begin", "warm_lu", "gathered", "basis", "swap_g",
+                                  "step_end", "final_begin", "final_end", "task_begin", "task_end",
+                                  "pivot", "swap_upd+red", "swap_xchg"};
+    const uint64_t n = std::min<uint64_t>(tr[0], (uint64_t)cap);
+    double tot[14] = {0};
+    int64_t cnt[14] = {0};
+    const double us_per_tick = 1000.0 / (double)ctx->wall_rate_khz;
+    for (uint64_t i = 1; i < n; ++i) {
+        const int ev = (int)(tr[1 + 2 * i] >> 56);
+        const double dt = (double)(tr[2 + 2 * i] - tr[2 + 2 * (i - 1)]) * us_per_tick;
+        if (ev > 0 && ev < 14) { tot[ev] += dt; cnt[ev] += 1; }
+    }
+    std::fprintf(stderr, "[lra trace] %llu events\n", (unsigned long long)n);
+    for (int e = 1; e < 14; ++e)
+        if (cnt[e])
+            std::fprintf(stderr, "[lra trace] %-12s n=%6lld total %9.1f us  mean %7.2f us\n", names[e],
+                         (long long)cnt[e], tot[e], tot[e] / (double)cnt[e]);
+}
+
 // Device workspace + upload + launch + download for a set of problems that
 // share precision and KMAX.  st_out / ij_out receive per-problem results.
 struct RunOut {
@@ -489,7 +529,8 @@ static lra_status run_problems(lra_ctx* ctx, std::vector<Prob>& probs, int prec6
     int kcap_all = 1;
     for (auto& p : probs) kcap_all = std::max(kcap_all, p.kcap);
     const int kmx = kmax_bucket(kcap_all);
-    const size_t smem = engine_smem_fixed(prec64, kmx) + (size_t)ctx->lds_b_bytes;
+    const int lds_b = strip_lds(ctx, prec64, kmx);
+    const size_t smem = engine_smem_fixed(prec64, kmx) + (size_t)lds_b;
     int occ = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, engine_kernel_ptr(prec64, kmx), NT, smem));
     if (occ < 1) return LRA_EDEVICE;
@@ -498,7 +539,7 @@ static lra_status run_problems(lra_ctx* ctx, std::vector<Prob>& probs, int prec6
         p.team = std::min(p.team, max_wgs);
         const int esz = prec64 ? 8 : 4;
         const int64_t R = (std::max(p.m, p.n) + p.team - 1) / p.team;
-        p.need_strip = R * p.kcap * esz > ctx->lds_b_bytes;
+        p.need_strip = R * p.kcap * esz > lds_b;
     }
     Plan pl = plan_teams(ctx, probs, max_wgs);
     const int grid = (int)pl.wg_team.size();
@@ -524,6 +565,8 @@ static lra_status run_problems(lra_ctx* ctx, std::vector<Prob>& probs, int prec6
     const int64_t off_ctl = L.add(ctl_stride * (int64_t)pl.teams.size());
     const int64_t off_qhead = L.add(4 * nq);
     const int64_t off_err = L.add(4);
+    const int trace_cap = ctx->trace ? 1 << 16 : 0;
+    const int64_t off_trace = L.add(8 * (1 + 2 * (int64_t)trace_cap));
     const int64_t total = L.size;
 
     lra_status rs = ensure(ctx->dev, total, false, ctx);
@@ -564,12 +607,20 @@ static lra_status run_problems(lra_ctx* ctx, std::vector<Prob>& probs, int prec6
     ea.team_ctl = d + off_ctl;
     ea.team_ctl_stride = ctl_stride;
     ea.phase_budget = phase_budget;
-    ea.lds_b_bytes = ctx->lds_b_bytes;
+    ea.lds_b_bytes = lds_b;
     ea.error_flag = (uint32_t*)(d + off_err);
     ea.timeout_ticks = (int64_t)(ctx->timeout_s * (double)ctx->wall_rate_khz * 1000.0);
+    ea.trace = trace_cap ? (uint64_t*)(d + off_trace) : nullptr;
+    ea.trace_cap = trace_cap;
+    ea.pad2 = 0;
     LRA_LOG(2, "launch: %zu problems, grid %d, teams %zu (max %d), smem %zu, coop %d", probs.size(), grid,
             pl.teams.size(), pl.max_team, smem, (int)coop);
+    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev0, ctx->stream));
     HIP_TRY(launch_engine(prec64, kmx, grid, smem, coop, ea, ctx->stream));
+    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev1, ctx->stream));
+    ctx->stats.launches += 1;
+    ctx->stats.last_grid = grid;
+    ctx->stats.last_teams = (int32_t)pl.teams.size();
 
     // download: states, index sets, G, U, error flag
     for (size_t i = 0; i < probs.size(); ++i) {
@@ -582,7 +633,17 @@ static lra_status run_problems(lra_ctx* ctx, std::vector<Prob>& probs, int prec6
             HIP_TRY(hipMemcpyAsync(h + r.off[j], d + r.off[j], 8 * kc * kc, hipMemcpyDeviceToHost, ctx->stream));
     }
     HIP_TRY(hipMemcpyAsync(h + off_err, d + off_err, 4, hipMemcpyDeviceToHost, ctx->stream));
+    if (trace_cap)
+        HIP_TRY(hipMemcpyAsync(h + off_trace, d + off_trace, 8 * (1 + 2 * (int64_t)trace_cap),
+                               hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (trace_cap) dump_trace(ctx, (const uint64_t*)(h + off_trace), trace_cap);
+    if (ctx->timing) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        ctx->stats.last_engine_ms = ms;
+        ctx->stats.engine_ms_total += ms;
+    }
     if (*(uint32_t*)(h + off_err)) {
         LRA_LOG(1, "device-side team barrier timed out");
         return LRA_EDEVICE;
@@ -649,7 +710,7 @@ extern "C" lra_status lra_ca_cur(lra_ctx* ctx, const lra_source* src, int64_t m,
     lra_status rs = make_prob(src, m, n, k, sweeps, tol, &o, probs[0], 0);
     if (rs != LRA_OK) return rs;
     const int prec64 = o.precision == LRA_PREC_FP64;
-    probs[0].team = o.team_wgs > 0 ? std::min(o.team_wgs, 1024) : auto_team(ctx, probs[0], prec64);
+    probs[0].team = o.team_wgs > 0 ? std::min(o.team_wgs, NT) : auto_team(ctx, probs[0], prec64);
     probs[0].C_out = result->C_out;
     probs[0].R_out = result->R_out;
     std::vector<RunOut> outs;
@@ -722,7 +783,7 @@ extern "C" lra_status lra_ca_cur_batched(lra_ctx* ctx, const lra_block* blocks, 
         const lra_block& bl = blocks[b];
         lra_status rs = make_prob(&bl.src, bl.m, bl.n, bl.k, bl.sweeps, bl.tol, &o, probs[b], b);
         if (rs != LRA_OK) return rs;
-        probs[b].team = o.team_wgs > 0 ? o.team_wgs : auto_team(ctx, probs[b], prec64);
+        probs[b].team = o.team_wgs > 0 ? std::min(o.team_wgs, NT) : auto_team(ctx, probs[b], prec64);
         probs[b].C_out = results[b].C_out;
         probs[b].R_out = results[b].R_out;
     }
@@ -766,10 +827,31 @@ extern "C" lra_status lra_wait(lra_ctx* ctx, uint64_t ticket)
     return LRA_EINVAL;
 }
 
+extern "C" lra_status lra_set_timing(lra_ctx* ctx, int enable, int reset)
+{
+    if (!ctx) return LRA_EINVAL;
+    if (enable && !ctx->ev0) {
+        HIP_TRY(hipEventCreate(&ctx->ev0));
+        HIP_TRY(hipEventCreate(&ctx->ev1));
+    }
+    ctx->timing = enable != 0;
+    if (reset) ctx->stats = lra_stats{};
+    return LRA_OK;
+}
+
+extern "C" lra_status lra_get_stats(lra_ctx* ctx, lra_stats* out)
+{
+    if (!ctx || !out) return LRA_EINVAL;
+    *out = ctx->stats;
+    return LRA_OK;
+}
+
 extern "C" void lra_destroy(lra_ctx* ctx)
 {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->dev.p) (void)hipFree(ctx->dev.p);
     if (ctx->host.p) (void)hipHostFree(ctx->host.p);
     delete ctx;

@@ -26,8 +26,8 @@ PREC_FP64, PREC_MIXED = 0, 1
 
 # every entry point declared in include/lra.h
 EXPORTS = ["lra_default_options", "lra_create", "lra_destroy", "lra_ca_cur", "lra_maxvol",
-           "lra_ca_cur_batched", "lra_submit", "lra_poll", "lra_wait", "lra_status_str",
-           "lra_version"]
+           "lra_ca_cur_batched", "lra_submit", "lra_poll", "lra_wait", "lra_set_timing",
+           "lra_get_stats", "lra_status_str", "lra_version"]
 
 
 class LraError(RuntimeError):
@@ -59,6 +59,12 @@ class ResultC(C.Structure):
                 ("err_est_abs", C.c_double), ("err_mean", C.c_double), ("err_var", C.c_double),
                 ("nucleus_cond1", C.c_double), ("t_submit_us", C.c_double),
                 ("t_start_us", C.c_double), ("t_end_us", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("engine_ms_total", C.c_double),
+                ("last_engine_ms", C.c_double), ("last_grid", C.c_int32),
+                ("last_teams", C.c_int32)]
 
 
 class Block(C.Structure):
@@ -104,6 +110,10 @@ def lib():
         L.lra_poll.restype = C.c_int
         L.lra_wait.argtypes = [P, C.c_uint64]
         L.lra_wait.restype = C.c_int
+        L.lra_set_timing.argtypes = [P, C.c_int, C.c_int]
+        L.lra_set_timing.restype = C.c_int
+        L.lra_get_stats.argtypes = [P, C.POINTER(Stats)]
+        L.lra_get_stats.restype = C.c_int
         L.lra_status_str.argtypes = [C.c_int]
         L.lra_status_str.restype = C.c_char_p
         L.lra_version.argtypes = []
@@ -271,6 +281,17 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    # -- kernel timing ----------------------------------------------------
+    def set_timing(self, enable: bool = True, reset: bool = True):
+        st = lib().lra_set_timing(self._h, 1 if enable else 0, 1 if reset else 0)
+        if st != OK:
+            raise LraError(st, "lra_set_timing")
+
+    def stats(self) -> dict:
+        s = Stats()
+        lib().lra_get_stats(self._h, C.byref(s))
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
 
     # -- one problem ------------------------------------------------------
     def ca_cur(self, src: DeviceSource, k: int, sweeps: int, tol: float = 0.0, *,
