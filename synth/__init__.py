@@ -112,3 +112,95 @@ def cauchy_points(seed: int = 0, m: int = 1 << 20, n: int | None = None, k: int 
     cand = rng.choice(n, min(n, 2 * max(k, k_max)), replace=False).astype(np.int64)
     Q, S = residual_sample(m, n, seed)
     return s.astype(dtype), t.astype(dtype), Draws(cand, Q, S)
+
+
+# ---------------------------------------------------------------------------
+# multipole-style workload: 1D points, adaptive binary tree, far-field blocks
+# (the neutered-block-column generators of the multipole application)
+# ---------------------------------------------------------------------------
+
+MIX_MEANS = (0.2, 0.5, 0.8)
+MIX_SDS = (0.01, 0.05, 0.1)
+
+
+def mixture_points(seed: int = 0, N: int = 1 << 20) -> np.ndarray:
+    """N points from the 3-component Gaussian mixture (equal weights, means
+    0.2/0.5/0.8, sds 0.01/0.05/0.1), clipped to [0, 1], sorted (float64).
+    Draw order: component labels, then the standard normals."""
+    rng = np.random.default_rng(seed)
+    comp = rng.integers(0, 3, N)
+    z = rng.standard_normal(N)
+    x = np.asarray(MIX_MEANS)[comp] + np.asarray(MIX_SDS)[comp] * z
+    return np.sort(np.clip(x, 0.0, 1.0))
+
+
+@dataclass
+class Box:
+    lo: float
+    hi: float
+    start: int
+    end: int
+    children: tuple = ()
+
+    @property
+    def count(self) -> int:
+        return self.end - self.start
+
+    @property
+    def width(self) -> float:
+        return self.hi - self.lo
+
+
+def build_tree(x: np.ndarray, leaf_max: int = 4096, lo: float = 0.0, hi: float = 1.0) -> Box:
+    """Adaptive binary tree on sorted points: a box [lo, hi) is split at its
+    midpoint while it holds more than leaf_max points."""
+    def make(lo, hi, start, end, depth):
+        b = Box(lo, hi, start, end)
+        if end - start > leaf_max and depth < 60:
+            mid = 0.5 * (lo + hi)
+            cut = start + int(np.searchsorted(x[start:end], mid, side="left"))
+            b.children = (make(lo, mid, start, cut, depth + 1), make(mid, hi, cut, end, depth + 1))
+        return b
+    return make(lo, hi, 0, len(x), 0)
+
+
+def far_field_blocks(root: Box, min_size: int = 96):
+    """Admissible pairs by dual-tree traversal: boxes X, Y with
+    dist(X, Y) >= max(width X, width Y).  Each unordered pair is listed once
+    (X left of Y); pairs with fewer than min_size points on a side are
+    returned separately as dense blocks.  Returns (blocks, dense) lists of
+    (x_start, x_end, y_start, y_end)."""
+    blocks, dense = [], []
+
+    def dist(a, b):
+        return max(0.0, b.lo - a.hi, a.lo - b.hi)
+
+    def visit(a, b):
+        if a.count == 0 or b.count == 0:
+            return
+        if a is b:
+            if not a.children:
+                return  # diagonal leaf: near field
+            c = a.children
+            visit(c[0], c[0])
+            visit(c[1], c[1])
+            visit(c[0], c[1])
+            return
+        if dist(a, b) >= max(a.width, b.width):
+            rec = (a.start, a.end, b.start, b.end)
+            if min(a.count, b.count) < min_size:
+                dense.append(rec)
+            else:
+                blocks.append(rec)
+            return
+        if not a.children and not b.children:
+            return  # near field
+        if a.children and (not b.children or a.width >= b.width):
+            for c in a.children:
+                visit(c, b)
+        else:
+            for c in b.children:
+                visit(a, c)
+
+    visit(root, root)
+    return blocks, dense
