@@ -653,7 +653,7 @@ NOINL double gather_phase(const TaskDesc& td, Team& tio, int transpose)
 
 // Partial-pivot LU of the strip (k team-wide pivot searches), then the rows
 // of L1 (unit lower) are left in AUG.  Returns the effective rank, or -1 if
-// the team failed / a pivot was exactly zero (status set).
+// the team failed or the strip has no nonzero entry at all (status set).
 template <typename T, int KMAX, bool LDSB>
 NOINL int gepp_phase(const TaskDesc& td, Team& tio, int transpose, double thresh)
 {
@@ -682,13 +682,13 @@ NOINL int gepp_phase(const TaskDesc& td, Team& tio, int transpose, double thresh
         if (tm.failed) { tio = tm; return -1; }
         __syncthreads();
         const double pav = k2_val(wv);
-        if (pav == 0.0) {
+        if (pav == 0.0 && t == 0) {  // a zero strip: no pivot at all
             if (threadIdx.x == 0) { sm.status = -2; sm.phase = PH_DONE; }
             __syncthreads();
             tio = tm;
             return -1;
         }
-        if (pav < thresh) { keff = t; break; }
+        if (pav < thresh || pav == 0.0) { keff = t; break; }
         if (threadIdx.x == 0) X[t] = k2_row(wv);
         // row t of L1: the pivot row's multipliers, a unit diagonal, zeros above
         if (threadIdx.x < k) AUG[t * LD + threadIdx.x] = threadIdx.x < t ? sm.pay[threadIdx.x] : (T)(threadIdx.x == t ? 1 : 0);

@@ -252,3 +252,23 @@ def test_k_equals_min_dim(ctx):
     assert res.status == ref.status == 0
     assert sorted(res.J.tolist()) == list(range(6))
     assert res.err_est_rel <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_dependent_columns(ctx, prec):
+    """A repeated / scaled column in the start set: rank loss, as the oracle."""
+    lra = _lra()
+    _say(f"dependent columns {prec}")
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((60, 40))
+    A[:, 7] = A[:, 3]
+    A[:, 11] = 2.0 * A[:, 5]
+    A = A.astype(np.float64 if prec == "f64" else np.float32)
+    for J0, kk in (([3, 5, 0, 7, 11], 3), ([3, 7, 5, 11, 0], 1)):
+        ref = oracle.ca_cur(oracle.dense(A), 5, 1, 0.0, J0, np.arange(60), np.arange(40), precision=prec)
+        res = ctx.ca_cur(lra.dense(torch.from_numpy(A).cuda()), 5, 1, 0.0, init_cols=J0,
+                         sample_rows=np.arange(60), sample_cols=np.arange(40),
+                         precision=lra.PREC_FP64 if prec == "f64" else lra.PREC_MIXED)
+        assert res.status == ref.status == lra.NUMERICAL_RANK and res.k == ref.k == kk
+        np.testing.assert_array_equal(res.J, ref.J)
+        np.testing.assert_array_equal(res.I, ref.I)

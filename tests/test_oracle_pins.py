@@ -398,6 +398,27 @@ def test_delta_matrices_appendix_e():
     assert r.status == -2
 
 
+def test_dependent_column_reduces_rank():
+    """The first step's LU takes the strip's columns in slot order: a
+    dependent column leaves no usable pivot, so the rank drops to the pivots
+    before it with NUMERICAL_RANK, whether rounding leaves that column exactly
+    zero or not; only a zero strip is FAILURE."""
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((60, 40))
+    A[:, 7] = A[:, 3]
+    A[:, 11] = 2.0 * A[:, 5]
+    for prec in ("f64", "f32"):
+        Ap = A.astype(np.float64 if prec == "f64" else np.float32)
+        r = oracle.ca_cur(oracle.dense(Ap), 5, 1, 0.0, [3, 5, 0, 7, 11], np.arange(60), np.arange(40),
+                          precision=prec)
+        assert r.status == 3 and r.k == 3, (prec, r.status, r.k)
+        # the three surviving columns are independent ones
+        assert len({3, 7} & set(r.J.tolist())) <= 1 and len({5, 11} & set(r.J.tolist())) <= 1
+        r = oracle.ca_cur(oracle.dense(Ap), 5, 1, 0.0, [3, 7, 5, 11, 0], np.arange(60), np.arange(40),
+                          precision=prec)
+        assert r.status == 3 and r.k == 1, (prec, r.status, r.k)
+
+
 def test_nonfinite_entry_reported():
     A, d = synth.plain_fp64(1)
     A = A.copy()
