@@ -47,10 +47,12 @@ typedef enum {
     LRA_OK = 0,
     LRA_TOL_NOT_MET = 1,    /* tol not reached at k_max (best result returned)       */
     LRA_MAXVOL_CAP = 2,     /* a maxvol call hit max_swaps                            */
-    LRA_NUMERICAL_RANK = 3, /* an LU pivot fell below 64 u max|strip|: k reduced      */
+    LRA_NUMERICAL_RANK = 3, /* an LU pivot fell below 64 u max|strip| (or was zero):
+                               k reduced to the pivots above it                       */
     LRA_PENDING = 4,        /* lra_poll: the ticket has not completed yet             */
     LRA_EINVAL = -1,        /* invalid argument                                       */
-    LRA_ERANK = -2,         /* exactly singular strip or generator (paper: FAILURE)   */
+    LRA_ERANK = -2,         /* zero strip (no nonzero pivot) or exactly singular
+                               generator (paper: FAILURE)                             */
     LRA_ENOMEM = -3,        /* device allocation failed                               */
     LRA_EBUDGET = -4,       /* request exceeds the context's HBM budget               */
     LRA_EDEVICE = -5,       /* HIP runtime error or device-side time-out              */
@@ -188,16 +190,37 @@ lra_status lra_maxvol(lra_ctx* ctx, const void* strip, int32_t dtype, int64_t m,
 lra_status lra_ca_cur_batched(lra_ctx* ctx, const lra_block* blocks, int nblocks,
                               const lra_options* opts, lra_result* results);
 
-/* Serving: submit a request (copied; its arrays must stay valid until it
- * completes); the context's scheduler admits it once its workspace fits the
- * HBM budget and a slot is free, and advances all admitted requests together
- * (continuous batching).  Errors at submit: LRA_EINVAL, LRA_EBUDGET (larger
- * than the whole budget). */
+/* Serving (continuous batching; the paper has no serving layer, this is the
+ * runtime around its C-A / CUR kernels).  Admitted requests own a region of a
+ * device arena (inputs, resumable state, results, a global strip); a tick
+ * launches the engine once per (precision, rank bucket) over every admitted
+ * request with a budget of a few phases each (a phase = one C-A step, or the
+ * nucleus + estimate), so requests of any size advance together and a new
+ * request joins at the next tick.  Waiting requests are admitted first come
+ * first served once their region fits.
+ *
+ * lra_submit: validates and copies the request (its source arrays and
+ *   `result` arrays must stay valid until it completes) and returns a ticket;
+ *   it may launch a tick but never waits for the device.  Errors: LRA_EINVAL,
+ *   LRA_EBUDGET (the request is larger than the whole arena), LRA_ENOMEM,
+ *   LRA_EDEVICE.
+ * lra_poll: finishes the in-flight tick if the device is done with it
+ *   (delivering completed requests into their lra_result, with host-clock
+ *   time stamps) and launches the next; never waits.  Returns LRA_PENDING,
+ *   or the completed request's status (every later call returns the same).
+ *   LRA_EINVAL for an unknown ticket.
+ * lra_wait: like lra_poll, but waits for ticks until the ticket completes.
+ * A device error fails every admitted and waiting request with LRA_EDEVICE. */
 lra_status lra_submit(lra_ctx* ctx, const lra_request* req, uint64_t* ticket);
-/* Advance the scheduler once; returns LRA_PENDING or the request's status. */
 lra_status lra_poll(lra_ctx* ctx, uint64_t ticket);
-/* Advance until the ticket completes; returns its status. */
 lra_status lra_wait(lra_ctx* ctx, uint64_t ticket);
+
+/* Serving configuration; 0 keeps a value.  arena_bytes: device arena for
+ * admitted requests (default min(4 GiB, budget / 2)); max_active: admitted
+ * requests at most (default 1024); both only before the first submit.
+ * phases_per_tick: phase budget of each request per tick (default 4).
+ * Errors: LRA_EINVAL. */
+lra_status lra_serve_config(lra_ctx* ctx, size_t arena_bytes, int phases_per_tick, int max_active);
 
 /* Kernel timing of a context.  With timing enabled, HIP events on the
  * context's stream bracket every engine launch; engine_ms_total accumulates
@@ -208,6 +231,7 @@ typedef struct lra_stats {
     double last_engine_ms;
     int32_t last_grid;           /* workgroups of the latest launch          */
     int32_t last_teams;          /* teams of the latest launch               */
+    int64_t ticks;               /* serving ticks                            */
 } lra_stats;
 /* enable: 1 on, 0 off; reset: zero the counters. */
 lra_status lra_set_timing(lra_ctx* ctx, int enable, int reset);

@@ -104,7 +104,7 @@ struct Buffer {
     int64_t bytes = 0;
 };
 
-struct Request;
+struct Serve;
 
 struct lra_ctx {
     int device = 0;
@@ -124,11 +124,7 @@ struct lra_ctx {
     bool trace = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     lra_stats stats{};
-    // serving
-    uint64_t next_ticket = 1;
-    std::deque<Request*> pending;
-    std::vector<Request*> active;
-    std::map<uint64_t, std::unique_ptr<Request>> all;
+    Serve* srv = nullptr;    // serving scheduler, created by the first serving call
 };
 
 static lra_status hip_fail(hipError_t e, const char* what)
@@ -352,9 +348,33 @@ static int auto_team(lra_ctx* ctx, const Prob& p, int prec64)
     return (int)std::max<int64_t>(1, t);
 }
 
-static void fill_task(TaskDesc& td, const Prob& p, uint8_t* dbase, const int64_t* offs)
+// ----------------------------------------------------------------------------
+// device regions of a problem
+// ----------------------------------------------------------------------------
+
+// Byte offsets of one problem's device regions, relative to a base pointer.
+struct ProbRegions {
+    int64_t cand = -1, Q = -1, S = -1;                       // inputs
+    int64_t st = -1, I = -1, J = -1;                         // resumable state
+    int64_t G = -1, U = -1;                                  // results
+    int64_t prevI = -1, prevJ = -1, work = -1, strip = -1;   // scratch (strip: -1 when unused)
+};
+
+// Final phase scratch: [G | I | A[I,S]] with row stride 2 KMAX + 64, and
+// the q x k and q x s sample blocks.
+static int64_t work_bytes(const Prob& p)
 {
-    // offs: cand, Q, S, I, J, prevI, prevJ, G, U, work, strip, state
+    const int64_t kb = kmax_bucket(p.kcap), kc = p.kcap;
+    return 8 * (kb * (2 * kb + 64) + (int64_t)p.q * kc + (int64_t)p.q * p.s);
+}
+
+static int64_t strip_bytes(const Prob& p, int prec64)
+{
+    return std::max(p.m, p.n) * (int64_t)p.kcap * (prec64 ? 8 : 4);
+}
+
+static void fill_task(TaskDesc& td, const Prob& p, uint8_t* base, const ProbRegions& r)
+{
     td.src = p.src;
     td.m = p.m;
     td.n = p.n;
@@ -368,67 +388,40 @@ static void fill_task(TaskDesc& td, const Prob& p, uint8_t* dbase, const int64_t
     td.warm_start = p.warm;
     td.q = p.q;
     td.s = p.s;
-    td.cand = (const int64_t*)(dbase + offs[0]);
+    td.cand = (const int64_t*)(base + r.cand);
     td.n_cand = (int64_t)p.cand.size();
-    td.Q = (const int64_t*)(dbase + offs[1]);
-    td.S = (const int64_t*)(dbase + offs[2]);
-    td.I = (int64_t*)(dbase + offs[3]);
-    td.J = (int64_t*)(dbase + offs[4]);
-    td.prevI = (int64_t*)(dbase + offs[5]);
-    td.prevJ = (int64_t*)(dbase + offs[6]);
-    td.G = (double*)(dbase + offs[7]);
-    td.U = (double*)(dbase + offs[8]);
-    td.work = (double*)(dbase + offs[9]);
-    td.strip = offs[10] >= 0 ? (void*)(dbase + offs[10]) : nullptr;
+    td.Q = (const int64_t*)(base + r.Q);
+    td.S = (const int64_t*)(base + r.S);
+    td.I = (int64_t*)(base + r.I);
+    td.J = (int64_t*)(base + r.J);
+    td.prevI = (int64_t*)(base + r.prevI);
+    td.prevJ = (int64_t*)(base + r.prevJ);
+    td.G = (double*)(base + r.G);
+    td.U = (double*)(base + r.U);
+    td.work = (double*)(base + r.work);
+    td.strip = r.strip >= 0 ? (void*)(base + r.strip) : nullptr;
     td.C_out = p.C_out;
     td.R_out = p.R_out;
-    td.st = (TaskState*)(dbase + offs[11]);
+    td.st = (TaskState*)(base + r.st);
 }
 
-// Offsets of one problem's device regions inside a layout.
-struct ProbRegions {
-    int64_t off[12];
-};
-
-static ProbRegions lay_prob(Layout& L, const Prob& p, int prec64)
+// Host image of the inputs (cand, Q, S) and of the initial state (st, I, J).
+static void init_inputs(uint8_t* h, const Prob& p, const ProbRegions& r)
 {
-    ProbRegions r;
-    const int64_t kc = p.kcap;
-    r.off[0] = L.add(8 * (int64_t)p.cand.size());
-    r.off[1] = L.add(8 * (int64_t)p.q);
-    r.off[2] = L.add(8 * (int64_t)p.s);
-    r.off[3] = L.add(8 * kc);
-    r.off[4] = L.add(8 * kc);
-    r.off[5] = L.add(8 * kc);
-    r.off[6] = L.add(8 * kc);
-    r.off[7] = L.add(8 * kc * kc);
-    r.off[8] = L.add(8 * kc * kc);
-    {
-        // final phase scratch: [G | I | A[I,S]] (row stride 2 KMAX + 64) and the sample blocks
-        const int64_t kb = kmax_bucket(p.kcap);
-        r.off[9] = L.add(8 * (kb * (2 * kb + 64) + (int64_t)p.q * kc + (int64_t)p.q * p.s));
-    }
-    r.off[10] = p.need_strip ? L.add(std::max(p.m, p.n) * kc * (prec64 ? 8 : 4)) : -1;
-    r.off[11] = L.add(sizeof(TaskState));
-    return r;
+    std::memcpy(h + r.cand, p.cand.data(), 8 * p.cand.size());
+    std::memcpy(h + r.Q, p.Q.data(), 8 * (size_t)p.q);
+    std::memcpy(h + r.S, p.S.data(), 8 * (size_t)p.s);
 }
 
-static void init_host_image(uint8_t* h, const Prob& p, const ProbRegions& r)
+static void init_state(uint8_t* h_st, uint8_t* h_I, uint8_t* h_J, const Prob& p)
 {
-    std::memcpy(h + r.off[0], p.cand.data(), 8 * p.cand.size());
-    std::memcpy(h + r.off[1], p.Q.data(), 8 * (size_t)p.q);
-    std::memcpy(h + r.off[2], p.S.data(), 8 * (size_t)p.s);
-    int64_t* I = (int64_t*)(h + r.off[3]);
-    int64_t* J = (int64_t*)(h + r.off[4]);
-    int64_t* pI = (int64_t*)(h + r.off[5]);
-    int64_t* pJ = (int64_t*)(h + r.off[6]);
+    int64_t* I = (int64_t*)h_I;
+    int64_t* J = (int64_t*)h_J;
     for (int c = 0; c < p.kcap; ++c) {
         I[c] = (p.have_init_I && c < p.k) ? p.init_I[c] : 0;
         J[c] = c < p.k ? p.cand[c] : 0;
-        pI[c] = 0;
-        pJ[c] = 0;
     }
-    TaskState* st = (TaskState*)(h + r.off[11]);
+    TaskState* st = (TaskState*)h_st;
     std::memset(st, 0, sizeof(*st));
     st->phase = PH_COL;
     st->k = p.k;
@@ -437,7 +430,7 @@ static void init_host_image(uint8_t* h, const Prob& p, const ProbRegions& r)
 }
 
 // ----------------------------------------------------------------------------
-// running a set of problems in one launch
+// team planning
 // ----------------------------------------------------------------------------
 
 struct Plan {
@@ -447,48 +440,128 @@ struct Plan {
     int max_team = 1;
 };
 
-// Teams by size class: each class gets teams in proportion to its work,
-// problems in a class are pulled largest first.
-static Plan plan_teams(lra_ctx* ctx, const std::vector<Prob>& probs, int max_wgs)
+static int pow2_ceil(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Teams by size class.  Every class first gets one team (the caller makes
+// the class sizes fit the grid); the remaining workgroups go to the classes
+// in proportion to their work, then greedily to the class with the most work
+// per team.  Problems of a class are pulled largest first.
+static Plan plan_teams(const std::vector<Prob*>& probs, int max_wgs)
 {
     Plan pl;
     std::map<int, std::vector<int32_t>> cls;
-    for (int i = 0; i < (int)probs.size(); ++i) cls[probs[i].team].push_back(i);
+    for (int i = 0; i < (int)probs.size(); ++i) cls[probs[i]->team].push_back(i);
+    auto cost_of = [&](int i) {
+        return (double)(probs[i]->m + probs[i]->n) * probs[i]->kcap * probs[i]->sweeps;
+    };
+    std::vector<int> size, nteam, nitems;
+    std::vector<double> cost;
+    int reserved = 0;
     double total = 0.0;
-    std::map<int, double> cost;
     for (auto& kv : cls) {
         double c = 0.0;
-        for (int i : kv.second) c += (double)(probs[i].m + probs[i].n) * probs[i].kcap * probs[i].sweeps;
-        cost[kv.first] = c;
+        for (int i : kv.second) c += cost_of(i);
+        size.push_back(kv.first);
+        nitems.push_back((int)kv.second.size());
+        cost.push_back(c);
+        nteam.push_back(1);
+        reserved += kv.first;
         total += c;
     }
+    const int nc = (int)size.size();
+    int avail = std::max(0, max_wgs - reserved);
+    for (int c = 0; c < nc; ++c) {
+        int extra = (int)std::floor((double)avail * cost[c] / std::max(total, 1.0) / size[c]);
+        extra = std::max(0, std::min(extra, nitems[c] - 1));
+        nteam[c] += extra;
+    }
     int used = 0;
-    int qi = 0;
+    for (int c = 0; c < nc; ++c) used += nteam[c] * size[c];
+    for (;;) {
+        int best = -1;
+        for (int c = 0; c < nc; ++c)
+            if (nteam[c] < nitems[c] && used + size[c] <= max_wgs &&
+                (best < 0 || cost[c] / nteam[c] > cost[best] / nteam[best]))
+                best = c;
+        if (best < 0) break;
+        nteam[best] += 1;
+        used += size[best];
+    }
+    int c = 0, wg = 0;
     for (auto& kv : cls) {
-        const int tsz = kv.first;
         auto items = kv.second;
-        std::stable_sort(items.begin(), items.end(), [&](int a, int b) {
-            return (probs[a].m + probs[a].n) * (int64_t)probs[a].kcap > (probs[b].m + probs[b].n) * (int64_t)probs[b].kcap;
-        });
-        int want = (int)std::floor((double)max_wgs * cost[kv.first] / std::max(total, 1.0) / tsz);
-        want = std::max(1, std::min<int>(want, (int)items.size()));
-        const int room = std::max(0, max_wgs - used) / tsz;
-        int nteam = std::max(1, std::min(want, room));
-        for (int t = 0; t < nteam; ++t) {
+        std::stable_sort(items.begin(), items.end(), [&](int a, int b) { return cost_of(a) > cost_of(b); });
+        for (int t = 0; t < nteam[c]; ++t) {
             TeamInfo ti;
-            ti.first_wg = used;
-            ti.size = tsz;
-            ti.queue = qi;
+            ti.first_wg = wg;
+            ti.size = size[c];
+            ti.queue = c;
             ti.pad = 0;
             pl.teams.push_back(ti);
-            for (int w = 0; w < tsz; ++w) pl.wg_team.push_back((int32_t)pl.teams.size() - 1);
-            used += tsz;
+            for (int w = 0; w < size[c]; ++w) pl.wg_team.push_back((int32_t)pl.teams.size() - 1);
+            wg += size[c];
         }
         pl.queues.push_back(items);
-        pl.max_team = std::max(pl.max_team, tsz);
-        ++qi;
+        pl.max_team = std::max(pl.max_team, size[c]);
+        ++c;
     }
     return pl;
+}
+
+struct LaunchPlan {
+    int kmx = 8;
+    int lds_b = 0;
+    int max_wgs = 0;
+    int grid = 0;
+    size_t smem = 0;
+    bool coop = false;
+    Plan pl;
+};
+
+// Fit the problems' teams to the co-resident grid of the (precision, KMAX)
+// kernel and plan the queues.  With fixed_strip the problems already own a
+// global strip region (serving), so any team size is safe; otherwise each
+// problem's need for one is decided here.
+static lra_status plan_launch(lra_ctx* ctx, std::vector<Prob*>& probs, int prec64, int kmx, bool fixed_strip,
+                              LaunchPlan& lp)
+{
+    lp.kmx = kmx;
+    lp.lds_b = strip_lds(ctx, prec64, kmx);
+    lp.smem = engine_smem_fixed(prec64, kmx) + (size_t)lp.lds_b;
+    int occ = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, engine_kernel_ptr(prec64, kmx), NT, lp.smem));
+    if (occ < 1) return LRA_EDEVICE;
+    lp.max_wgs = occ * ctx->num_cu;
+    for (Prob* p : probs) p->team = std::max(1, std::min(p->team, lp.max_wgs));
+    // every size class holds at least one team: halve the largest sizes until
+    // the classes fit the grid together
+    for (;;) {
+        std::vector<int> sizes;
+        for (Prob* p : probs) sizes.push_back(p->team);
+        std::sort(sizes.begin(), sizes.end());
+        sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+        int64_t sum = 0;
+        for (int s : sizes) sum += s;
+        if (sum <= lp.max_wgs) break;
+        const int big = sizes.back();
+        for (Prob* p : probs)
+            if (p->team == big) p->team = std::max(1, big / 2);
+    }
+    const int esz = prec64 ? 8 : 4;
+    for (Prob* p : probs) {
+        if (fixed_strip) continue;
+        const int64_t R = (std::max(p->m, p->n) + p->team - 1) / p->team;
+        p->need_strip = R * p->kcap * esz > lp.lds_b;
+    }
+    lp.pl = plan_teams(probs, lp.max_wgs);
+    lp.grid = (int)lp.pl.wg_team.size();
+    lp.coop = lp.pl.max_team > 1;
+    return LRA_OK;
 }
 
 // Summarise a device trace on stderr: time spent before each event kind,
@@ -514,153 +587,89 @@ static void dump_trace(lra_ctx* ctx, const uint64_t* tr, int cap)
                          (long long)cnt[e], tot[e], tot[e] / (double)cnt[e]);
 }
 
-// Device workspace + upload + launch + download for a set of problems that
-// share precision and KMAX.  st_out / ij_out receive per-problem results.
-struct RunOut {
-    TaskState st;
-    std::vector<int64_t> I, J;
-    std::vector<double> G, U;
+// ----------------------------------------------------------------------------
+// control image of one launch
+// ----------------------------------------------------------------------------
+
+struct CtlImage {
+    int64_t tasks = 0, items = 0, qoff = 0, qlen = 0, teams = 0, wgteam = 0;  // uploaded
+    int64_t ctl = 0, qhead = 0;                                             // zero-filled
+    int64_t ctl_stride = 0;
+    int nq = 0;
 };
 
-static lra_status run_problems(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, int phase_budget,
-                               std::vector<RunOut>& outs)
+static void lay_ctl_upload(Layout& L, CtlImage& c, size_t ntasks, const Plan& pl)
 {
-    if (probs.empty()) return LRA_OK;
-    int kcap_all = 1;
-    for (auto& p : probs) kcap_all = std::max(kcap_all, p.kcap);
-    const int kmx = kmax_bucket(kcap_all);
-    const int lds_b = strip_lds(ctx, prec64, kmx);
-    const size_t smem = engine_smem_fixed(prec64, kmx) + (size_t)lds_b;
-    int occ = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, engine_kernel_ptr(prec64, kmx), NT, smem));
-    if (occ < 1) return LRA_EDEVICE;
-    const int max_wgs = occ * ctx->num_cu;
-    for (auto& p : probs) {
-        p.team = std::min(p.team, max_wgs);
-        const int esz = prec64 ? 8 : 4;
-        const int64_t R = (std::max(p.m, p.n) + p.team - 1) / p.team;
-        p.need_strip = R * p.kcap * esz > lds_b;
-    }
-    Plan pl = plan_teams(ctx, probs, max_wgs);
-    const int grid = (int)pl.wg_team.size();
-    const bool coop = pl.max_team > 1;
-
-    // layout: [upload: tasks | per-problem regions | queues | teams | wg_team]
-    //         [zeroed: team ctl | queue heads | error flag]
-    Layout L;
-    const int64_t off_tasks = L.add(sizeof(TaskDesc) * probs.size());
-    std::vector<ProbRegions> regs;
-    regs.reserve(probs.size());
-    for (auto& p : probs) regs.push_back(lay_prob(L, p, prec64));
     int64_t nitems = 0;
     for (auto& q : pl.queues) nitems += (int64_t)q.size();
-    const int nq = (int)pl.queues.size();
-    const int64_t off_items = L.add(4 * std::max<int64_t>(1, nitems));
-    const int64_t off_qoff = L.add(4 * nq);
-    const int64_t off_qlen = L.add(4 * nq);
-    const int64_t off_teams = L.add(sizeof(TeamInfo) * pl.teams.size());
-    const int64_t off_wgteam = L.add(4 * (int64_t)grid);
-    const int64_t upload_end = L.size;
-    const int64_t ctl_stride = align_up(team_ctl_bytes(pl.max_team), 256);
-    const int64_t off_ctl = L.add(ctl_stride * (int64_t)pl.teams.size());
-    const int64_t off_qhead = L.add(4 * nq);
-    const int64_t off_err = L.add(4);
-    const int trace_cap = ctx->trace ? 1 << 16 : 0;
-    const int64_t off_trace = L.add(8 * (1 + 2 * (int64_t)trace_cap));
-    const int64_t total = L.size;
+    c.nq = (int)pl.queues.size();
+    c.tasks = L.add(sizeof(TaskDesc) * ntasks);
+    c.items = L.add(4 * std::max<int64_t>(1, nitems));
+    c.qoff = L.add(4 * c.nq);
+    c.qlen = L.add(4 * c.nq);
+    c.teams = L.add(sizeof(TeamInfo) * pl.teams.size());
+    c.wgteam = L.add(4 * (int64_t)pl.wg_team.size());
+}
 
-    lra_status rs = ensure(ctx->dev, total, false, ctx);
-    if (rs != LRA_OK) return rs;
-    rs = ensure(ctx->host, total, true, ctx);
-    if (rs != LRA_OK) return rs;
-    uint8_t* h = (uint8_t*)ctx->host.p;
-    uint8_t* d = (uint8_t*)ctx->dev.p;
+static void lay_ctl_zero(Layout& L, CtlImage& c, const Plan& pl)
+{
+    c.ctl_stride = align_up(team_ctl_bytes(pl.max_team), 256);
+    c.ctl = L.add(c.ctl_stride * (int64_t)pl.teams.size());
+    c.qhead = L.add(4 * (int64_t)c.nq);
+}
 
-    TaskDesc* htasks = (TaskDesc*)(h + off_tasks);
-    for (size_t i = 0; i < probs.size(); ++i) {
-        init_host_image(h, probs[i], regs[i]);
-        fill_task(htasks[i], probs[i], d, regs[i].off);
-    }
-    int32_t* items = (int32_t*)(h + off_items);
-    int32_t* qoff = (int32_t*)(h + off_qoff);
-    int32_t* qlen = (int32_t*)(h + off_qlen);
+static void write_ctl(uint8_t* h, const CtlImage& c, const Plan& pl)
+{
+    int32_t* items = (int32_t*)(h + c.items);
+    int32_t* qoff = (int32_t*)(h + c.qoff);
+    int32_t* qlen = (int32_t*)(h + c.qlen);
     int64_t pos = 0;
-    for (int q = 0; q < nq; ++q) {
+    for (int q = 0; q < c.nq; ++q) {
         qoff[q] = (int32_t)pos;
         qlen[q] = (int32_t)pl.queues[q].size();
         for (int32_t t : pl.queues[q]) items[pos++] = t;
     }
-    std::memcpy(h + off_teams, pl.teams.data(), sizeof(TeamInfo) * pl.teams.size());
-    std::memcpy(h + off_wgteam, pl.wg_team.data(), 4 * (size_t)grid);
+    std::memcpy(h + c.teams, pl.teams.data(), sizeof(TeamInfo) * pl.teams.size());
+    std::memcpy(h + c.wgteam, pl.wg_team.data(), 4 * pl.wg_team.size());
+}
 
-    HIP_TRY(hipMemcpyAsync(d, h, (size_t)upload_end, hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(launch_zero(d + off_ctl, total - off_ctl, ctx->stream));
-
+static EngineArgs engine_args(lra_ctx* ctx, uint8_t* d, const CtlImage& c, const LaunchPlan& lp, int phase_budget,
+                              uint32_t* err, uint64_t* trace, int trace_cap)
+{
     EngineArgs ea;
-    ea.tasks = (TaskDesc*)(d + off_tasks);
-    ea.queue_items = (const int32_t*)(d + off_items);
-    ea.queue_off = (const int32_t*)(d + off_qoff);
-    ea.queue_len = (const int32_t*)(d + off_qlen);
-    ea.queue_head = (uint32_t*)(d + off_qhead);
-    ea.teams = (const TeamInfo*)(d + off_teams);
-    ea.wg_team = (const int32_t*)(d + off_wgteam);
-    ea.team_ctl = d + off_ctl;
-    ea.team_ctl_stride = ctl_stride;
+    ea.tasks = (TaskDesc*)(d + c.tasks);
+    ea.queue_items = (const int32_t*)(d + c.items);
+    ea.queue_off = (const int32_t*)(d + c.qoff);
+    ea.queue_len = (const int32_t*)(d + c.qlen);
+    ea.queue_head = (uint32_t*)(d + c.qhead);
+    ea.teams = (const TeamInfo*)(d + c.teams);
+    ea.wg_team = (const int32_t*)(d + c.wgteam);
+    ea.team_ctl = d + c.ctl;
+    ea.team_ctl_stride = c.ctl_stride;
     ea.phase_budget = phase_budget;
-    ea.lds_b_bytes = lds_b;
-    ea.error_flag = (uint32_t*)(d + off_err);
+    ea.lds_b_bytes = lp.lds_b;
+    ea.error_flag = err;
     ea.timeout_ticks = (int64_t)(ctx->timeout_s * (double)ctx->wall_rate_khz * 1000.0);
-    ea.trace = trace_cap ? (uint64_t*)(d + off_trace) : nullptr;
+    ea.trace = trace;
     ea.trace_cap = trace_cap;
     ea.pad2 = 0;
-    LRA_LOG(2, "launch: %zu problems, grid %d, teams %zu (max %d), smem %zu, coop %d", probs.size(), grid,
-            pl.teams.size(), pl.max_team, smem, (int)coop);
-    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev0, ctx->stream));
-    HIP_TRY(launch_engine(prec64, kmx, grid, smem, coop, ea, ctx->stream));
-    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev1, ctx->stream));
-    ctx->stats.launches += 1;
-    ctx->stats.last_grid = grid;
-    ctx->stats.last_teams = (int32_t)pl.teams.size();
+    return ea;
+}
 
-    // download: states, index sets, G, U, error flag
-    for (size_t i = 0; i < probs.size(); ++i) {
-        const auto& r = regs[i];
-        const int64_t kc = probs[i].kcap;
-        HIP_TRY(hipMemcpyAsync(h + r.off[11], d + r.off[11], sizeof(TaskState), hipMemcpyDeviceToHost, ctx->stream));
-        for (int j = 3; j <= 4; ++j)
-            HIP_TRY(hipMemcpyAsync(h + r.off[j], d + r.off[j], 8 * kc, hipMemcpyDeviceToHost, ctx->stream));
-        for (int j = 7; j <= 8; ++j)
-            HIP_TRY(hipMemcpyAsync(h + r.off[j], d + r.off[j], 8 * kc * kc, hipMemcpyDeviceToHost, ctx->stream));
-    }
-    HIP_TRY(hipMemcpyAsync(h + off_err, d + off_err, 4, hipMemcpyDeviceToHost, ctx->stream));
-    if (trace_cap)
-        HIP_TRY(hipMemcpyAsync(h + off_trace, d + off_trace, 8 * (1 + 2 * (int64_t)trace_cap),
-                               hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    if (trace_cap) dump_trace(ctx, (const uint64_t*)(h + off_trace), trace_cap);
-    if (ctx->timing) {
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-        ctx->stats.last_engine_ms = ms;
-        ctx->stats.engine_ms_total += ms;
-    }
-    if (*(uint32_t*)(h + off_err)) {
-        LRA_LOG(1, "device-side team barrier timed out");
-        return LRA_EDEVICE;
-    }
-    outs.resize(probs.size());
-    for (size_t i = 0; i < probs.size(); ++i) {
-        const auto& r = regs[i];
-        RunOut& o = outs[i];
-        o.st = *(TaskState*)(h + r.off[11]);
-        const int k = o.st.k;
-        o.I.assign((int64_t*)(h + r.off[3]), (int64_t*)(h + r.off[3]) + k);
-        o.J.assign((int64_t*)(h + r.off[4]), (int64_t*)(h + r.off[4]) + k);
-        o.G.assign((double*)(h + r.off[7]), (double*)(h + r.off[7]) + (int64_t)k * k);
-        o.U.assign((double*)(h + r.off[8]), (double*)(h + r.off[8]) + (int64_t)k * k);
-    }
+static lra_status launch(lra_ctx* ctx, int prec64, const LaunchPlan& lp, const EngineArgs& ea, hipStream_t stream)
+{
+    LRA_LOG(2, "launch: grid %d, teams %zu (max %d), smem %zu, coop %d", lp.grid, lp.pl.teams.size(),
+            lp.pl.max_team, lp.smem, (int)lp.coop);
+    HIP_TRY(launch_engine(prec64, lp.kmx, lp.grid, lp.smem, lp.coop, ea, stream));
+    ctx->stats.launches += 1;
+    ctx->stats.last_grid = lp.grid;
+    ctx->stats.last_teams = (int32_t)lp.pl.teams.size();
     return LRA_OK;
 }
+
+// ----------------------------------------------------------------------------
+// results
+// ----------------------------------------------------------------------------
 
 static lra_status status_of(const TaskState& st)
 {
@@ -671,28 +680,142 @@ static lra_status status_of(const TaskState& st)
     return LRA_OK;
 }
 
-static void deliver(const RunOut& o, lra_result* res)
+static void deliver(const TaskState& st, const int64_t* I, const int64_t* J, const double* G, const double* U,
+                    lra_result* res)
 {
-    res->k = o.st.k;
-    res->status = (int32_t)status_of(o.st);
-    res->sweeps_done = o.st.sweeps_done;
-    res->swaps_total = o.st.swaps_total;
-    res->entries_read = o.st.entries_read;
-    res->err_est_rel = o.st.est_rel;
-    res->err_est_abs = o.st.est_abs;
-    res->err_mean = o.st.mean;
-    res->err_var = o.st.var;
-    res->nucleus_cond1 = o.st.cond1;
-    if (res->I) std::memcpy(res->I, o.I.data(), 8 * o.I.size());
-    if (res->J) std::memcpy(res->J, o.J.data(), 8 * o.J.size());
-    if (res->G) std::memcpy(res->G, o.G.data(), 8 * o.G.size());
-    if (res->U) std::memcpy(res->U, o.U.data(), 8 * o.U.size());
+    const int k = st.k;
+    res->k = k;
+    res->status = (int32_t)status_of(st);
+    res->sweeps_done = st.sweeps_done;
+    res->swaps_total = st.swaps_total;
+    res->entries_read = st.entries_read;
+    res->err_est_rel = st.est_rel;
+    res->err_est_abs = st.est_abs;
+    res->err_mean = st.mean;
+    res->err_var = st.var;
+    res->nucleus_cond1 = st.cond1;
+    if (res->I && I) std::memcpy(res->I, I, 8 * (size_t)k);
+    if (res->J && J) std::memcpy(res->J, J, 8 * (size_t)k);
+    if (res->G && G) std::memcpy(res->G, G, 8 * (size_t)k * k);
+    if (res->U && U) std::memcpy(res->U, U, 8 * (size_t)k * k);
 }
 
 static int severity(lra_status s)
 {
     if (s < 0) return 100 - (int)s;
     return (int)s;
+}
+
+// ----------------------------------------------------------------------------
+// blocking runs: a set of problems of one precision in one launch
+// ----------------------------------------------------------------------------
+
+// Image layout (one workspace buffer):
+//   upload    : control | inputs (cand, Q, S) | states | I | J | error word
+//   read back : states | I | J | error word, then G | U when asked for
+//   zeroed    : team control blocks, queue heads, trace
+//   scratch   : prevI, prevJ, final-phase work, global strips
+static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, int phase_budget,
+                            lra_result* const* res)
+{
+    const size_t np = probs.size();
+    if (np == 0) return LRA_OK;
+    int kcap_all = 1;
+    for (auto& p : probs) kcap_all = std::max(kcap_all, p.kcap);
+    std::vector<Prob*> pp;
+    for (auto& p : probs) pp.push_back(&p);
+    LaunchPlan lp;
+    lra_status rs = plan_launch(ctx, pp, prec64, kmax_bucket(kcap_all), false, lp);
+    if (rs != LRA_OK) return rs;
+    bool want_G = false, want_U = false;
+    for (size_t i = 0; i < np; ++i) {
+        want_G = want_G || res[i]->G;
+        want_U = want_U || res[i]->U;
+    }
+
+    Layout L;
+    CtlImage c;
+    lay_ctl_upload(L, c, np, lp.pl);
+    std::vector<ProbRegions> regs(np);
+    for (size_t i = 0; i < np; ++i) {
+        regs[i].cand = L.add(8 * (int64_t)probs[i].cand.size(), 8);
+        regs[i].Q = L.add(8 * (int64_t)probs[i].q, 8);
+        regs[i].S = L.add(8 * (int64_t)probs[i].s, 8);
+    }
+    const int64_t rb0 = L.add(0);
+    for (size_t i = 0; i < np; ++i) regs[i].st = L.add(sizeof(TaskState), 8);
+    for (size_t i = 0; i < np; ++i) regs[i].I = L.add(8 * (int64_t)probs[i].kcap, 8);
+    for (size_t i = 0; i < np; ++i) regs[i].J = L.add(8 * (int64_t)probs[i].kcap, 8);
+    const int64_t off_err = L.add(8, 8);
+    const int64_t up_end = L.size;
+    for (size_t i = 0; i < np; ++i) regs[i].G = L.add(8 * (int64_t)probs[i].kcap * probs[i].kcap, 8);
+    const int64_t u0 = L.add(0, 8);
+    for (size_t i = 0; i < np; ++i) regs[i].U = L.add(8 * (int64_t)probs[i].kcap * probs[i].kcap, 8);
+    const int64_t u1 = L.size;
+    const int64_t z0 = L.add(0);
+    lay_ctl_zero(L, c, lp.pl);
+    const int trace_cap = ctx->trace ? 1 << 16 : 0;
+    const int64_t off_trace = L.add(8 * (1 + 2 * (int64_t)trace_cap));
+    const int64_t z1 = L.size;
+    for (size_t i = 0; i < np; ++i) {
+        regs[i].prevI = L.add(8 * (int64_t)probs[i].kcap);
+        regs[i].prevJ = L.add(8 * (int64_t)probs[i].kcap);
+        regs[i].work = L.add(work_bytes(probs[i]));
+        regs[i].strip = probs[i].need_strip ? L.add(strip_bytes(probs[i], prec64)) : -1;
+    }
+    const int64_t total = L.size;
+
+    rs = ensure(ctx->dev, total, false, ctx);
+    if (rs != LRA_OK) return rs;
+    rs = ensure(ctx->host, u1, true, ctx);
+    if (rs != LRA_OK) return rs;
+    uint8_t* h = (uint8_t*)ctx->host.p;
+    uint8_t* d = (uint8_t*)ctx->dev.p;
+
+    write_ctl(h, c, lp.pl);
+    TaskDesc* htasks = (TaskDesc*)(h + c.tasks);
+    for (size_t i = 0; i < np; ++i) {
+        init_inputs(h, probs[i], regs[i]);
+        init_state(h + regs[i].st, h + regs[i].I, h + regs[i].J, probs[i]);
+        fill_task(htasks[i], probs[i], d, regs[i]);
+    }
+    *(uint64_t*)(h + off_err) = 0;
+
+    HIP_TRY(hipMemcpyAsync(d, h, (size_t)up_end, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(launch_zero(d + z0, z1 - z0, ctx->stream));
+    EngineArgs ea = engine_args(ctx, d, c, lp, phase_budget, (uint32_t*)(d + off_err),
+                                trace_cap ? (uint64_t*)(d + off_trace) : nullptr, trace_cap);
+    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev0, ctx->stream));
+    rs = launch(ctx, prec64, lp, ea, ctx->stream);
+    if (rs != LRA_OK) return rs;
+    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev1, ctx->stream));
+
+    const int64_t rb1 = want_U ? u1 : want_G ? u0 : up_end;
+    HIP_TRY(hipMemcpyAsync(h + rb0, d + rb0, (size_t)(rb1 - rb0), hipMemcpyDeviceToHost, ctx->stream));
+    std::vector<uint64_t> trace_host;
+    if (trace_cap) {
+        trace_host.resize(1 + 2 * (size_t)trace_cap);
+        HIP_TRY(hipMemcpyAsync(trace_host.data(), d + off_trace, 8 * trace_host.size(), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (trace_cap) dump_trace(ctx, trace_host.data(), trace_cap);
+    if (ctx->timing) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        ctx->stats.last_engine_ms = ms;
+        ctx->stats.engine_ms_total += ms;
+    }
+    if (*(uint32_t*)(h + off_err)) {
+        LRA_LOG(1, "device-side team barrier timed out");
+        return LRA_EDEVICE;
+    }
+    for (size_t i = 0; i < np; ++i) {
+        const ProbRegions& r = regs[i];
+        deliver(*(const TaskState*)(h + r.st), (const int64_t*)(h + r.I), (const int64_t*)(h + r.J),
+                want_G ? (const double*)(h + r.G) : nullptr, want_U ? (const double*)(h + r.U) : nullptr, res[i]);
+    }
+    return LRA_OK;
 }
 
 // ----------------------------------------------------------------------------
@@ -713,10 +836,9 @@ extern "C" lra_status lra_ca_cur(lra_ctx* ctx, const lra_source* src, int64_t m,
     probs[0].team = o.team_wgs > 0 ? std::min(o.team_wgs, NT) : auto_team(ctx, probs[0], prec64);
     probs[0].C_out = result->C_out;
     probs[0].R_out = result->R_out;
-    std::vector<RunOut> outs;
-    rs = run_problems(ctx, probs, prec64, 1 << 30, outs);
+    lra_result* rp = result;
+    rs = run_batch(ctx, probs, prec64, 1 << 30, &rp);
     if (rs != LRA_OK) return rs;
-    deliver(outs[0], result);
     return (lra_status)result->status;
 }
 
@@ -757,15 +879,18 @@ extern "C" lra_status lra_maxvol(lra_ctx* ctx, const void* strip, int32_t dtype,
     }
     const int prec64 = dtype == LRA_F64;
     probs[0].team = auto_team(ctx, probs[0], prec64);
-    std::vector<RunOut> outs;
-    rs = run_problems(ctx, probs, prec64, 1, outs);
+    lra_result r;
+    std::memset(&r, 0, sizeof(r));
+    std::vector<int64_t> Iout(k);
+    r.I = Iout.data();
+    lra_result* rp = &r;
+    rs = run_batch(ctx, probs, prec64, 1, &rp);
     if (rs != LRA_OK) return rs;
-    const TaskState& st = outs[0].st;
-    if (st.status < 0) return (lra_status)st.status;
-    for (int c = 0; c < st.k; ++c) I[c] = outs[0].I[c];
-    if (swaps) *swaps = st.swaps_total;
-    if (k_eff) *k_eff = st.k;
-    return status_of(st);
+    if (r.status < 0) return (lra_status)r.status;
+    for (int c = 0; c < r.k; ++c) I[c] = Iout[c];
+    if (swaps) *swaps = r.swaps_total;
+    if (k_eff) *k_eff = r.k;
+    return (lra_status)r.status;
 }
 
 extern "C" lra_status lra_ca_cur_batched(lra_ctx* ctx, const lra_block* blocks, int nblocks, const lra_options* opts,
@@ -779,52 +904,478 @@ extern "C" lra_status lra_ca_cur_batched(lra_ctx* ctx, const lra_block* blocks, 
     if (o.init_cols || o.sample_rows || o.sample_cols) return LRA_EINVAL;
     const int prec64 = o.precision == LRA_PREC_FP64;
     std::vector<Prob> probs(nblocks);
+    std::vector<lra_result*> rp(nblocks);
     for (int b = 0; b < nblocks; ++b) {
         const lra_block& bl = blocks[b];
         lra_status rs = make_prob(&bl.src, bl.m, bl.n, bl.k, bl.sweeps, bl.tol, &o, probs[b], b);
         if (rs != LRA_OK) return rs;
-        probs[b].team = o.team_wgs > 0 ? std::min(o.team_wgs, NT) : auto_team(ctx, probs[b], prec64);
+        // power-of-two team sizes keep the number of size classes small
+        probs[b].team = o.team_wgs > 0 ? std::min(o.team_wgs, NT)
+                                       : std::min(NT, pow2_ceil(auto_team(ctx, probs[b], prec64)));
         probs[b].C_out = results[b].C_out;
         probs[b].R_out = results[b].R_out;
+        rp[b] = &results[b];
     }
-    std::vector<RunOut> outs;
-    lra_status rs = run_problems(ctx, probs, prec64, 1 << 30, outs);
+    lra_status rs = run_batch(ctx, probs, prec64, 1 << 30, rp.data());
     if (rs != LRA_OK) return rs;
     lra_status worst = LRA_OK;
-    for (int b = 0; b < nblocks; ++b) {
-        deliver(outs[b], &results[b]);
+    for (int b = 0; b < nblocks; ++b)
         if (severity((lra_status)results[b].status) > severity(worst)) worst = (lra_status)results[b].status;
-    }
     return worst;
 }
 
 // ----------------------------------------------------------------------------
-// serving (continuous batching) -- filled in by lra_serve.cpp
+// serving: continuous batching of independent requests
 // ----------------------------------------------------------------------------
+//
+// Admitted requests own a region of a device arena (inputs, state, results,
+// scratch, a global strip) and a slot of a state table at the arena's start.
+// A tick launches the engine once per (precision, KMAX) group over every
+// admitted request with a budget of a few phases each (a phase is one column
+// step, one row step, or the nucleus + estimate); the engine leaves each
+// request's resumable state in HBM.  When the tick has finished, the state
+// table comes back in one copy; completed requests are delivered and release
+// their region, waiting requests are admitted first come first served, and
+// the next tick is launched.  lra_poll never waits for the device.
 
 struct Request {
-    uint64_t ticket;
-    lra_request req;
-    lra_result* res;
-    lra_status status = LRA_PENDING;
+    uint64_t ticket = 0;
+    lra_result* res = nullptr;
+    Prob p;
+    int prec64 = 1;
+    int kmx = 8;
+    int team = 1;
+    int64_t footprint = 0;
+    int64_t arena_off = -1;
+    int slot = -1;
+    ProbRegions r;      // offsets relative to the arena base
+    double t_submit = 0.0, t_start = 0.0;
 };
+
+// First-fit allocator over [0, size).
+struct FreeList {
+    std::map<int64_t, int64_t> free;  // offset -> bytes
+    void reset(int64_t size)
+    {
+        free.clear();
+        if (size > 0) free[0] = size;
+    }
+    int64_t alloc(int64_t bytes)
+    {
+        for (auto it = free.begin(); it != free.end(); ++it) {
+            if (it->second < bytes) continue;
+            const int64_t off = it->first, left = it->second - bytes;
+            free.erase(it);
+            if (left > 0) free[off + bytes] = left;
+            return off;
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t bytes)
+    {
+        auto it = free.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free.erase(nx);
+        }
+        if (it != free.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free.erase(it);
+            }
+        }
+    }
+};
+
+struct Serve {
+    Buffer arena;                 // device: state table, then request regions
+    Buffer ctl_dev;               // device: control images of a tick
+    Buffer host;                  // pinned: control images, admitted inputs, read-back
+    int64_t arena_bytes = 0;      // 0: chosen at the first submit
+    int64_t table_bytes = 0;
+    int phases_per_tick = 4;
+    int max_active = 1024;
+    FreeList fl;
+    std::vector<int> free_slots;
+    std::deque<Request*> pending;
+    std::vector<Request*> active;
+    std::map<uint64_t, std::unique_ptr<Request>> live;
+    std::map<uint64_t, lra_status> done;
+    uint64_t next_ticket = 1;
+    bool in_flight = false;
+    bool failed = false;
+    hipEvent_t ev = nullptr;
+    int64_t tick_tbl_off = 0;       // host staging offsets of the in-flight tick's
+    int64_t tick_err_off = 0;       // state table and error words
+    int tick_groups = 0;
+    int64_t ticks = 0;
+};
+
+static int64_t request_footprint(const Prob& p, int prec64)
+{
+    Layout L;
+    L.add(8 * (int64_t)p.cand.size(), 8);
+    L.add(8 * (int64_t)p.q, 8);
+    L.add(8 * (int64_t)p.s, 8);
+    L.add(8 * (int64_t)p.kcap, 8);
+    L.add(8 * (int64_t)p.kcap, 8);
+    L.add(8 * (int64_t)p.kcap * p.kcap, 8);
+    L.add(8 * (int64_t)p.kcap * p.kcap, 8);
+    L.add(8 * (int64_t)p.kcap);
+    L.add(8 * (int64_t)p.kcap);
+    L.add(work_bytes(p));
+    L.add(strip_bytes(p, prec64));
+    return align_up(L.size, 256);
+}
+
+// Region of an admitted request: [cand | Q | S | I | J | G | U] then scratch;
+// [cand .. J] is uploaded at admission, [I .. U] read back at completion.
+static ProbRegions request_regions(const Prob& p, int prec64, int64_t base)
+{
+    Layout L;
+    L.size = base;
+    ProbRegions r;
+    r.cand = L.add(8 * (int64_t)p.cand.size(), 8);
+    r.Q = L.add(8 * (int64_t)p.q, 8);
+    r.S = L.add(8 * (int64_t)p.s, 8);
+    r.I = L.add(8 * (int64_t)p.kcap, 8);
+    r.J = L.add(8 * (int64_t)p.kcap, 8);
+    r.G = L.add(8 * (int64_t)p.kcap * p.kcap, 8);
+    r.U = L.add(8 * (int64_t)p.kcap * p.kcap, 8);
+    r.prevI = L.add(8 * (int64_t)p.kcap);
+    r.prevJ = L.add(8 * (int64_t)p.kcap);
+    r.work = L.add(work_bytes(p));
+    r.strip = L.add(strip_bytes(p, prec64));
+    return r;
+}
+
+static lra_status serve_init(lra_ctx* ctx)
+{
+    Serve& s = *ctx->srv;
+    if (s.arena.p) return LRA_OK;
+    if (s.arena_bytes <= 0) {
+        const int64_t def = 4ll << 30;
+        s.arena_bytes = ctx->budget ? std::min<int64_t>(def, (int64_t)ctx->budget / 2) : def;
+    }
+    s.table_bytes = align_up((int64_t)s.max_active * (int64_t)sizeof(TaskState), 256);
+    if (s.arena_bytes <= s.table_bytes) return LRA_EBUDGET;
+    if (ctx->budget && (size_t)(s.arena_bytes + ctx->dev.bytes) > ctx->budget) return LRA_EBUDGET;
+    if (hipMalloc(&s.arena.p, (size_t)s.arena_bytes) != hipSuccess) {
+        s.arena.p = nullptr;
+        return LRA_ENOMEM;
+    }
+    s.arena.bytes = s.arena_bytes;
+    ctx->dev_in_use += s.arena_bytes;
+    s.fl.reset(s.arena_bytes - s.table_bytes);
+    s.free_slots.clear();
+    for (int i = s.max_active - 1; i >= 0; --i) s.free_slots.push_back(i);
+    HIP_TRY(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+    return LRA_OK;
+}
+
+static void finish_request(lra_ctx* ctx, Request* q, lra_status st)
+{
+    Serve& s = *ctx->srv;
+    q->res->status = (int32_t)st;
+    q->res->t_submit_us = q->t_submit;
+    q->res->t_start_us = q->t_start;
+    q->res->t_end_us = now_us();
+    if (q->arena_off >= 0) s.fl.release(q->arena_off, q->footprint);
+    if (q->slot >= 0) s.free_slots.push_back(q->slot);
+    s.done[q->ticket] = st;
+    s.live.erase(q->ticket);
+}
+
+// Launch one tick: admit what fits, then one engine launch per group.
+static lra_status serve_launch(lra_ctx* ctx)
+{
+    Serve& s = *ctx->srv;
+    // admission, first come first served (the head of the queue blocks)
+    std::vector<Request*> admitted;
+    while (!s.pending.empty() && !s.free_slots.empty()) {
+        Request* q = s.pending.front();
+        const int64_t off = s.fl.alloc(q->footprint);
+        if (off < 0) break;
+        s.pending.pop_front();
+        q->arena_off = off;
+        q->slot = s.free_slots.back();
+        s.free_slots.pop_back();
+        q->r = request_regions(q->p, q->prec64, s.table_bytes + off);
+        q->r.st = (int64_t)q->slot * (int64_t)sizeof(TaskState);
+        q->t_start = now_us();
+        s.active.push_back(q);
+        admitted.push_back(q);
+    }
+    if (s.active.empty()) return LRA_OK;
+
+    // groups by (precision, KMAX)
+    std::map<std::pair<int, int>, std::vector<Request*>> groups;
+    for (Request* q : s.active) groups[{q->prec64, q->kmx}].push_back(q);
+    struct G {
+        int prec64;
+        LaunchPlan lp;
+        CtlImage c;
+        std::vector<Request*> reqs;
+    };
+    std::vector<G> gs;
+    Layout L;   // control images, device and host alike
+    for (auto& kv : groups) {
+        G g;
+        g.prec64 = kv.first.first;
+        g.reqs = kv.second;
+        std::vector<Prob*> pp;
+        for (Request* q : g.reqs) {
+            q->p.team = q->team;
+            pp.push_back(&q->p);
+        }
+        lra_status rs = plan_launch(ctx, pp, g.prec64, kv.first.second, true, g.lp);
+        if (rs != LRA_OK) return rs;
+        lay_ctl_upload(L, g.c, g.reqs.size(), g.lp.pl);
+        gs.push_back(std::move(g));
+    }
+    const int64_t ctl_up_end = L.size;
+    const int64_t zero0 = L.add(0);
+    for (auto& g : gs) lay_ctl_zero(L, g.c, g.lp.pl);
+    const int64_t err_off = L.add(8 * (int64_t)gs.size(), 8);
+    const int64_t zero1 = L.size;
+    const int64_t dev_bytes = L.size;
+    // host staging: control images, then admitted requests' uploads, then the state table read-back
+    std::vector<int64_t> adm_off(admitted.size());
+    for (size_t i = 0; i < admitted.size(); ++i) {
+        Request* q = admitted[i];
+        adm_off[i] = L.add(q->r.G - q->r.cand + sizeof(TaskState));
+    }
+    int max_slot = 0;
+    for (Request* q : s.active) max_slot = std::max(max_slot, q->slot + 1);
+    const int64_t tbl_off = L.add((int64_t)max_slot * (int64_t)sizeof(TaskState));
+    const int64_t err_rb = L.add(8 * (int64_t)gs.size(), 8);
+    lra_status rs = ensure(s.ctl_dev, dev_bytes, false, ctx);
+    if (rs != LRA_OK) return rs;
+    rs = ensure(s.host, L.size, true, ctx);
+    if (rs != LRA_OK) return rs;
+    uint8_t* h = (uint8_t*)s.host.p;
+    uint8_t* dc = (uint8_t*)s.ctl_dev.p;
+    uint8_t* da = (uint8_t*)s.arena.p;
+
+    // uploads of admitted requests: [cand .. J] and the state slot
+    for (size_t i = 0; i < admitted.size(); ++i) {
+        Request* q = admitted[i];
+        const ProbRegions& r = q->r;
+        uint8_t* hb = h + adm_off[i] - r.cand;   // host image addressed like the arena
+        init_inputs(hb, q->p, r);
+        uint8_t* hst = h + adm_off[i] + (r.G - r.cand);
+        init_state(hst, hb + r.I, hb + r.J, q->p);
+        HIP_TRY(hipMemcpyAsync(da + r.cand, h + adm_off[i], (size_t)(r.G - r.cand), hipMemcpyHostToDevice,
+                               ctx->stream));
+        HIP_TRY(hipMemcpyAsync(da + r.st, hst, sizeof(TaskState), hipMemcpyHostToDevice, ctx->stream));
+    }
+    for (size_t gi = 0; gi < gs.size(); ++gi) {
+        G& g = gs[gi];
+        write_ctl(h, g.c, g.lp.pl);
+        TaskDesc* td = (TaskDesc*)(h + g.c.tasks);
+        for (size_t i = 0; i < g.reqs.size(); ++i) fill_task(td[i], g.reqs[i]->p, da, g.reqs[i]->r);
+    }
+    HIP_TRY(hipMemcpyAsync(dc, h, (size_t)ctl_up_end, hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(launch_zero(dc + zero0, zero1 - zero0, ctx->stream));
+    for (size_t gi = 0; gi < gs.size(); ++gi) {
+        G& g = gs[gi];
+        EngineArgs ea = engine_args(ctx, dc, g.c, g.lp, s.phases_per_tick, (uint32_t*)(dc + err_off + 8 * gi),
+                                    nullptr, 0);
+        rs = launch(ctx, g.prec64, g.lp, ea, ctx->stream);
+        if (rs != LRA_OK) return rs;
+    }
+    HIP_TRY(hipMemcpyAsync(h + tbl_off, da, (size_t)max_slot * sizeof(TaskState), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    HIP_TRY(hipMemcpyAsync(h + err_rb, dc + err_off, 8 * gs.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipEventRecord(s.ev, ctx->stream));
+    s.in_flight = true;
+    s.tick_tbl_off = tbl_off;
+    s.tick_err_off = err_rb;
+    s.tick_groups = (int)gs.size();
+    s.ticks += 1;
+    ctx->stats.ticks += 1;
+    return LRA_OK;
+}
+
+static void serve_fail_all(lra_ctx* ctx, lra_status st)
+{
+    Serve& s = *ctx->srv;
+    for (Request* q : s.active) finish_request(ctx, q, st);
+    s.active.clear();
+    while (!s.pending.empty()) {
+        Request* q = s.pending.front();
+        s.pending.pop_front();
+        finish_request(ctx, q, st);
+    }
+}
+
+// The in-flight tick has finished: deliver the completed requests.
+static lra_status serve_complete(lra_ctx* ctx)
+{
+    Serve& s = *ctx->srv;
+    s.in_flight = false;
+    const uint8_t* h = (const uint8_t*)s.host.p;
+    bool dev_err = false;
+    for (int g = 0; g < s.tick_groups; ++g)
+        if (*(const uint32_t*)(h + s.tick_err_off + 8 * g)) dev_err = true;
+    if (dev_err) {
+        LRA_LOG(1, "device-side team barrier timed out while serving");
+        serve_fail_all(ctx, LRA_EDEVICE);
+        return LRA_EDEVICE;
+    }
+    const TaskState* tbl = (const TaskState*)(h + s.tick_tbl_off);
+    std::vector<Request*> fin, keep;
+    std::vector<TaskState> fst;
+    for (Request* q : s.active) {
+        const TaskState& st = tbl[q->slot];
+        if (st.phase == PH_DONE || st.status < 0) {
+            fin.push_back(q);
+            fst.push_back(st);
+        } else {
+            keep.push_back(q);
+        }
+    }
+    s.active = keep;
+    if (fin.empty()) return LRA_OK;
+    // read back [I | J | G | U] of every completed request
+    Layout L;
+    std::vector<int64_t> off(fin.size());
+    for (size_t i = 0; i < fin.size(); ++i) {
+        const ProbRegions& r = fin[i]->r;
+        off[i] = L.add(r.U + 8 * (int64_t)fin[i]->p.kcap * fin[i]->p.kcap - r.I);
+    }
+    lra_status rs = ensure(s.host, L.size, true, ctx);
+    if (rs != LRA_OK) return rs;
+    uint8_t* hh = (uint8_t*)s.host.p;
+    const uint8_t* da = (const uint8_t*)s.arena.p;
+    for (size_t i = 0; i < fin.size(); ++i) {
+        const ProbRegions& r = fin[i]->r;
+        const int64_t bytes = r.U + 8 * (int64_t)fin[i]->p.kcap * fin[i]->p.kcap - r.I;
+        HIP_TRY(hipMemcpyAsync(hh + off[i], da + r.I, (size_t)bytes, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (size_t i = 0; i < fin.size(); ++i) {
+        Request* q = fin[i];
+        const ProbRegions& r = q->r;
+        const uint8_t* b = hh + off[i] - r.I;
+        deliver(fst[i], (const int64_t*)(b + r.I), (const int64_t*)(b + r.J), (const double*)(b + r.G),
+                (const double*)(b + r.U), q->res);
+        finish_request(ctx, q, status_of(fst[i]));
+    }
+    return LRA_OK;
+}
+
+// Advance the scheduler: finish the in-flight tick if it is done (or wait
+// for it when `block`), then launch the next one when work remains.
+static lra_status serve_progress(lra_ctx* ctx, bool block)
+{
+    Serve& s = *ctx->srv;
+    if (s.in_flight) {
+        if (!block) {
+            const hipError_t q = hipEventQuery(s.ev);
+            if (q == hipErrorNotReady) return LRA_OK;
+            if (q != hipSuccess) {
+                serve_fail_all(ctx, LRA_EDEVICE);
+                return hip_fail(q, "hipEventQuery");
+            }
+        } else {
+            const hipError_t q = hipEventSynchronize(s.ev);
+            if (q != hipSuccess) {
+                serve_fail_all(ctx, LRA_EDEVICE);
+                return hip_fail(q, "hipEventSynchronize");
+            }
+        }
+        lra_status rs = serve_complete(ctx);
+        if (rs < 0) return rs;
+    }
+    if (!s.active.empty() || !s.pending.empty()) {
+        lra_status rs = serve_launch(ctx);
+        if (rs < 0) {
+            (void)hipStreamSynchronize(ctx->stream);
+            s.in_flight = false;
+            serve_fail_all(ctx, rs);
+            return rs;
+        }
+    }
+    return LRA_OK;
+}
+
+extern "C" lra_status lra_serve_config(lra_ctx* ctx, size_t arena_bytes, int phases_per_tick, int max_active)
+{
+    if (!ctx || phases_per_tick < 0 || max_active < 0) return LRA_EINVAL;
+    if (!ctx->srv) ctx->srv = new Serve();
+    Serve& s = *ctx->srv;
+    if (s.arena.p && ((arena_bytes && (int64_t)arena_bytes != s.arena_bytes) ||
+                      (max_active && max_active != s.max_active)))
+        return LRA_EINVAL;
+    if (arena_bytes) s.arena_bytes = (int64_t)arena_bytes;
+    if (max_active) s.max_active = max_active;
+    if (phases_per_tick) s.phases_per_tick = phases_per_tick;
+    return LRA_OK;
+}
 
 extern "C" lra_status lra_submit(lra_ctx* ctx, const lra_request* req, uint64_t* ticket)
 {
-    (void)ctx; (void)req; (void)ticket;
-    return LRA_EINVAL;
+    if (!ctx || !req || !ticket || !req->result) return LRA_EINVAL;
+    if (!ctx->srv) ctx->srv = new Serve();
+    Serve& s = *ctx->srv;
+    if (s.failed) return LRA_EDEVICE;
+    auto q = std::make_unique<Request>();
+    lra_status rs = make_prob(&req->src, req->m, req->n, req->k, req->sweeps, req->tol, &req->opts, q->p, 0);
+    if (rs != LRA_OK) return rs;
+    q->prec64 = req->opts.precision == LRA_PREC_FP64;
+    q->team = req->opts.team_wgs > 0 ? std::min(req->opts.team_wgs, NT)
+                                     : std::min(NT, pow2_ceil(auto_team(ctx, q->p, q->prec64)));
+    q->kmx = kmax_bucket(q->p.kcap);
+    q->p.need_strip = true;
+    q->p.C_out = req->result->C_out;
+    q->p.R_out = req->result->R_out;
+    q->footprint = request_footprint(q->p, q->prec64);
+    rs = serve_init(ctx);
+    if (rs != LRA_OK) return rs;
+    if (q->footprint > s.arena_bytes - s.table_bytes) return LRA_EBUDGET;
+    q->ticket = s.next_ticket++;
+    q->res = req->result;
+    q->res->status = LRA_PENDING;
+    q->t_submit = now_us();
+    *ticket = q->ticket;
+    s.pending.push_back(q.get());
+    s.live[q->ticket] = std::move(q);
+    rs = serve_progress(ctx, false);
+    return rs < 0 ? rs : LRA_OK;
 }
 
 extern "C" lra_status lra_poll(lra_ctx* ctx, uint64_t ticket)
 {
-    (void)ctx; (void)ticket;
-    return LRA_EINVAL;
+    if (!ctx || !ctx->srv) return LRA_EINVAL;
+    Serve& s = *ctx->srv;
+    auto d = s.done.find(ticket);
+    if (d != s.done.end()) return d->second;
+    if (!s.live.count(ticket)) return LRA_EINVAL;
+    lra_status rs = serve_progress(ctx, false);
+    d = s.done.find(ticket);
+    if (d != s.done.end()) return d->second;
+    return rs < 0 ? rs : LRA_PENDING;
 }
 
 extern "C" lra_status lra_wait(lra_ctx* ctx, uint64_t ticket)
 {
-    (void)ctx; (void)ticket;
-    return LRA_EINVAL;
+    if (!ctx || !ctx->srv) return LRA_EINVAL;
+    Serve& s = *ctx->srv;
+    for (;;) {
+        auto d = s.done.find(ticket);
+        if (d != s.done.end()) return d->second;
+        if (!s.live.count(ticket)) return LRA_EINVAL;
+        const bool had_work = s.in_flight || !s.active.empty() || !s.pending.empty();
+        lra_status rs = serve_progress(ctx, true);
+        if (rs < 0) {
+            d = s.done.find(ticket);
+            return d != s.done.end() ? d->second : rs;
+        }
+        if (!had_work) return LRA_EDEVICE;  // nothing could advance the ticket
+    }
 }
 
 extern "C" lra_status lra_set_timing(lra_ctx* ctx, int enable, int reset)
@@ -850,6 +1401,13 @@ extern "C" void lra_destroy(lra_ctx* ctx)
 {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
+    if (Serve* s = ctx->srv) {
+        if (s->ev) (void)hipEventDestroy(s->ev);
+        if (s->arena.p) (void)hipFree(s->arena.p);
+        if (s->ctl_dev.p) (void)hipFree(s->ctl_dev.p);
+        if (s->host.p) (void)hipHostFree(s->host.p);
+        delete s;
+    }
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->dev.p) (void)hipFree(ctx->dev.p);

@@ -26,7 +26,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 
 # every entry point declared in include/lra.h
 EXPORTS = ["lra_default_options", "lra_create", "lra_destroy", "lra_ca_cur", "lra_maxvol",
-           "lra_ca_cur_batched", "lra_submit", "lra_poll", "lra_wait", "lra_set_timing",
+           "lra_ca_cur_batched", "lra_submit", "lra_poll", "lra_wait", "lra_serve_config", "lra_set_timing",
            "lra_get_stats", "lra_status_str", "lra_version"]
 
 
@@ -64,7 +64,7 @@ class ResultC(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("launches", C.c_int64), ("engine_ms_total", C.c_double),
                 ("last_engine_ms", C.c_double), ("last_grid", C.c_int32),
-                ("last_teams", C.c_int32)]
+                ("last_teams", C.c_int32), ("ticks", C.c_int64)]
 
 
 class Block(C.Structure):
@@ -110,6 +110,8 @@ def lib():
         L.lra_poll.restype = C.c_int
         L.lra_wait.argtypes = [P, C.c_uint64]
         L.lra_wait.restype = C.c_int
+        L.lra_serve_config.argtypes = [P, C.c_size_t, C.c_int, C.c_int]
+        L.lra_serve_config.restype = C.c_int
         L.lra_set_timing.argtypes = [P, C.c_int, C.c_int]
         L.lra_set_timing.restype = C.c_int
         L.lra_get_stats.argtypes = [P, C.POINTER(Stats)]
@@ -381,8 +383,25 @@ class Context:
         return st, out
 
     # -- serving ----------------------------------------------------------
-    def submit(self, src: DeviceSource, k: int, sweeps: int, tol: float = 0.0, **opts) -> int:
+    def serve_config(self, arena_bytes: int = 0, phases_per_tick: int = 0, max_active: int = 0):
+        st = lib().lra_serve_config(self._h, int(arena_bytes), int(phases_per_tick), int(max_active))
+        if st != OK:
+            raise LraError(st, "lra_serve_config")
+
+    def submit(self, src: DeviceSource, k: int, sweeps: int, tol: float = 0.0, *,
+               init_cols=None, sample_rows=None, sample_cols=None, **opts) -> int:
+        """Queue one request; returns its ticket (see poll / wait)."""
         o = default_options(**opts)
+        cand, Q, S = _i64(init_cols), _i64(sample_rows), _i64(sample_cols)
+        if cand is not None:
+            o.init_cols = cand.ctypes.data
+            o.n_init_cols = len(cand)
+        if Q is not None:
+            o.sample_rows = Q.ctypes.data
+            o.sample_q = len(Q)
+        if S is not None:
+            o.sample_cols = S.ctypes.data
+            o.sample_s = len(S)
         buf = _ResultBuf(max(int(k), o.k_max))
         req = RequestC()
         req.src = src.struct
@@ -400,14 +419,21 @@ class Context:
         self._keep[t.value] = (buf, src)
         return t.value
 
-    def poll(self, ticket: int):
+    def poll(self, ticket: int) -> Optional[Result]:
+        """None while pending, else the Result (status < 0 for a failed request)."""
         st = lib().lra_poll(self._h, ticket)
         if st == PENDING:
             return None
+        if ticket not in self._keep:
+            raise LraError(st, "lra_poll")
         buf, _ = self._keep.pop(ticket)
+        buf.c.status = st
         return buf.to_result()
 
     def wait(self, ticket: int) -> Result:
-        lib().lra_wait(self._h, ticket)
+        st = lib().lra_wait(self._h, ticket)
+        if ticket not in self._keep:
+            raise LraError(st, "lra_wait")
         buf, _ = self._keep.pop(ticket)
+        buf.c.status = st
         return buf.to_result()

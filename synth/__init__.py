@@ -204,3 +204,73 @@ def far_field_blocks(root: Box, min_size: int = 96):
 
     visit(root, root)
     return blocks, dense
+
+
+def multipole(seed: int = 0, N: int = 1 << 20, leaf_max: int = 4096, min_size: int = 96):
+    """The batched far-field workload: sorted mixture points, the adaptive
+    tree, and its admissible blocks (x_start, x_end, y_start, y_end) with
+    min(|X|, |Y|) >= min_size; the smaller pairs stay dense."""
+    x = mixture_points(seed, N)
+    root = build_tree(x, leaf_max)
+    blocks, dense = far_field_blocks(root, min_size)
+    return x, blocks, dense
+
+
+def block_draws(seed: int, index: int):
+    """Stream seed of block `index` in a batched call (the library's default
+    draws use SplitMix64 stream seed + index * 0x1000003)."""
+    return (seed + index * 0x1000003) & 0xFFFFFFFFFFFFFFFF
+
+
+# ---------------------------------------------------------------------------
+# served stream: request specifications
+# ---------------------------------------------------------------------------
+
+@dataclass
+class RequestSpec:
+    kind: str          # "dense" or "cauchy"
+    m: int
+    n: int
+    k: int
+    tol: float
+    dtype: str         # "f32" or "f64"
+    arrival: float     # seconds after the stream starts
+    pool: int          # dense: index of the pool matrix (rank k, dtype); cauchy: point-set seed
+
+
+def request_stream(seed: int = 0, count: int = 2000, rate: float = 0.0, lo: int = 1024, hi: int = 65536,
+                   ks=(8, 16, 32, 64), tol_lo: float = 1e-10, tol_hi: float = 1e-4):
+    """Poisson arrivals at `rate` requests/s (rate 0: all arrive at t = 0).
+    Draw order per request: kind (p = 1/2), m, n (log-uniform [lo, hi]), k
+    (uniform over ks, capped at min(m, n)), tol (log-uniform), dtype (p = 1/2);
+    the exponential inter-arrival gaps are drawn afterwards."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        kind = "dense" if rng.random() < 0.5 else "cauchy"
+        m = int(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        n = int(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        k = int(min(ks[int(rng.integers(0, len(ks)))], m, n))
+        tol = float(np.exp(rng.uniform(np.log(tol_lo), np.log(tol_hi))))
+        dtype = "f32" if rng.random() < 0.5 else "f64"
+        specs.append(RequestSpec(kind, m, n, k, tol, dtype, 0.0, 0))
+    gaps = rng.exponential(1.0 / rate, count) if rate > 0 else np.zeros(count)
+    t = np.cumsum(gaps)
+    for i, s in enumerate(specs):
+        s.arrival = float(t[i]) if rate > 0 else 0.0
+        s.pool = ks.index(s.k) if s.k in ks else 0
+        if s.kind == "cauchy":
+            s.pool = i
+    return specs
+
+
+def dense_pool_matrix(seed: int, m: int, n: int, r: int, rel_noise: float, dtype=np.float64):
+    """Gaussian rank-r product plus Gaussian noise scaled to rel_noise of its
+    Frobenius norm (host, for test-sized pools).  Draw order: G1, G2, E."""
+    rng = np.random.default_rng(seed)
+    G1 = rng.standard_normal((m, r))
+    G2 = rng.standard_normal((r, n))
+    E = rng.standard_normal((m, n))
+    L = G1 @ G2
+    A = L + rel_noise * (np.linalg.norm(L) / np.linalg.norm(E)) * E
+    return A.astype(dtype)
