@@ -180,7 +180,8 @@ struct Team {
     uint8_t* ctl;
     int size;
     int rank;
-    uint32_t epoch;
+    uint32_t epoch;   // team barriers passed
+    uint32_t xepoch;  // argmax exchanges done
     bool failed;
     int tog;  // LDS double-buffer selector of block_argmax
     uint32_t* err;
@@ -257,31 +258,57 @@ DI void team_barrier(Team& tm, Smem<T, KMAX>& sm)
 }
 
 // Team-wide argmax: publish this workgroup's best key and its candidate row
-// (sm.pay[0..n)), then every workgroup reduces all slots and loads the
-// winning row (owner = row / rows_per_wg) into sm.pay.  With one workgroup
-// the local result is final.
+// (sm.pay[0..n)) in its own slot, stamped with the exchange number; thread i
+// of every workgroup waits for slot i's stamp, so no counter is contended.
+// Then every workgroup reduces all slots and loads the winning row (owner =
+// row / rows_per_wg) into sm.pay.  Slots alternate between two banks: a
+// workgroup can only publish exchange x + 1 after every slot of exchange x
+// arrived, i.e. after every workgroup finished reading exchange x - 1.  With
+// one workgroup the local result is final.
 template <typename T, int KMAX>
 DI K2 team_argmax(Team& tm, Smem<T, KMAX>& sm, const K2& mine, int n, int64_t rows_per_wg)
 {
     if (tm.size == 1) return mine;
-    const int par = tm.epoch & 1;
+    const int par = tm.xepoch & 1;
+    const uint32_t stamp = tm.xepoch + 1;
+    tm.xepoch = stamp;
     uint8_t* my = slot_ptr(tm, par, tm.rank);
     double* mypay = (double*)(my + 32);
+    // written by wavefront 0 only: its release below orders all of them
     if (threadIdx.x < n)
         __hip_atomic_store(mypay + threadIdx.x, (double)sm.pay[threadIdx.x], __ATOMIC_RELAXED, AGENT);
     if (threadIdx.x == 0) {
         __hip_atomic_store((uint64_t*)my, mine.hi, __ATOMIC_RELAXED, AGENT);
         __hip_atomic_store((uint64_t*)(my + 8), mine.lo, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store((uint32_t*)(my + 16), stamp, __ATOMIC_RELEASE, AGENT);
     }
-    team_barrier(tm, sm);
-    if (tm.failed) return k2_none();
+    // a slot that never arrives yields the reserved key K2_FAIL, which wins
+    // the reduction (keys of moduli, +inf included, have smaller hi words)
     K2 o = k2_none();
     if (threadIdx.x < tm.size) {
         const uint8_t* sp = slot_ptr(tm, par, threadIdx.x);
-        o.hi = __hip_atomic_load((uint64_t*)sp, __ATOMIC_RELAXED, AGENT);
-        o.lo = __hip_atomic_load((uint64_t*)(sp + 8), __ATOMIC_RELAXED, AGENT);
+        const int64_t t0 = wall_clock64();
+        bool bad = false;
+        while (__hip_atomic_load((const uint32_t*)(sp + 16), __ATOMIC_ACQUIRE, AGENT) != stamp) {
+            __builtin_amdgcn_s_sleep(1);
+            if (wall_clock64() - t0 > tm.timeout) {
+                atomicOr(tm.err, 1u);
+                bad = true;
+                break;
+            }
+        }
+        if (bad) {
+            o = K2{~0ull, ~0ull};
+        } else {
+            o.hi = __hip_atomic_load((const uint64_t*)sp, __ATOMIC_RELAXED, AGENT);
+            o.lo = __hip_atomic_load((const uint64_t*)(sp + 8), __ATOMIC_RELAXED, AGENT);
+        }
     }
     const K2 best = block_argmax(o, sm, tm);
+    if (best.hi == ~0ull) {
+        tm.failed = true;
+        return k2_none();
+    }
     if (n > 0) {
         const int w = (int)(k2_row(best) / rows_per_wg);
         if (threadIdx.x < n) {
@@ -306,15 +333,15 @@ struct Rows {
 };
 
 // Gather rows [r0, r0 + nrows) of the strip: column step A[:, F], row step
-// A[F, :]^T.  Returns this thread's max |entry| (+inf if an entry is not
-// finite).
+// A[F, :]^T, by threads tid of nth.  Returns this thread's max |entry| (+inf
+// if an entry is not finite).
 template <typename T, int KMAX>
 DI double gather_rows(const DevSource& s, int transpose, const Smem<T, KMAX>& sm, const int64_t* F, int k,
-                      const Rows<T>& rw)
+                      const Rows<T>& rw, int tid, int nth)
 {
     constexpr int CH = KMAX < 32 ? KMAX : 32;  // columns loaded together
     double lmax = 0.0;
-    for (int r = threadIdx.x; r < rw.nrows; r += NT) {
+    for (int r = tid; r < rw.nrows; r += nth) {
         const int64_t gi = rw.r0 + r;
         const double own = s.kind == 0 ? 0.0 : (transpose ? load_elem(s.y, s.dtype, gi) : load_elem(s.x, s.dtype, gi));
         for (int c0 = 0; c0 < k; c0 += CH) {
@@ -343,132 +370,162 @@ DI double gather_rows(const DevSource& s, int transpose, const Smem<T, KMAX>& sm
 }
 
 // ----------------------------------------------------------------------------
-// k x k partial-pivot LU by one wavefront (call from all 64 lanes of wave 0).
-// Lane s holds row s in place; candidates are compared as in LAPACK getrf
-// with physical row interchanges: larger modulus, then smaller current
-// position.  perm[t] = row chosen at step t, so factored row t is
-// LU[perm[t]][:] (L below the diagonal with a unit diagonal, U on and above).
-// Writes *ok (0 on an exact zero pivot) and the smallest pivot modulus.
+// small dense solves by one wavefront
 // ----------------------------------------------------------------------------
+
+// Orders the LDS accesses of wavefront 0 across lanes: the lanes of a
+// wavefront execute in lockstep and LDS serves one wavefront's requests in
+// order, so it suffices that the compiler keeps program order here.
+DI void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+DI double readlane_t(double v, int lane)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    return __longlong_as_double((long long)readlane64(b, lane));
+}
+
+DI float readlane_t(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
 
 // Solve M X = R for the k x k matrix M held in columns [0, k) of A (row
 // stride LD) and the nr right-hand sides in columns [rhs0, rhs0 + nr):
 // partial-pivot LU with the elimination carried along on the right-hand
 // sides (rows interchanged in place, pivots chosen as in LAPACK getrf:
 // larger modulus, then smaller position), then back substitution.  On
-// return row t of the right-hand-side block holds unknown t.  All threads of
-// the workgroup take part (three barriers per elimination step, two per
-// substitution step).  Writes sm.ok (0 on an exact zero pivot) and
-// sm.minpiv (the smallest pivot modulus).
+// return row t of the right-hand-side block holds unknown t.
+//
+// Wavefront 0 does the whole solve with no workgroup barrier inside: for
+// the pivot search and the multipliers lane s stands for row s (k <= 64);
+// for the updates lane c owns the columns c, c + 64, ... still in use, and
+// the multiplier of row s reaches every lane by a lane read.  Lanes without
+// a column of their own address column t instead, which is dead by then
+// (its rows past the pivot are never read again), so the loads and stores
+// need no per-lane branches and stay pipelined.  lu_aug_solve is called by
+// the whole workgroup (barriers on entry and exit), lu_aug_wave0 by
+// wavefront 0 alone.  Writes sm.ok (0 on an exact zero pivot) and sm.minpiv
+// (the smallest pivot modulus).
+template <typename T, int KMAX, typename LT, int LD, int NB>
+DI void lu_aug_wave0(LT* A, int k, int rhs0, int nr, Smem<T, KMAX>& sm)
+{
+    {
+        const int lane = threadIdx.x;
+        double minpiv = INFINITY;
+        int ok = 1;
+        LT dreg = (LT)0;  // lane t keeps pivot t
+        for (int t = 0; t < k; ++t) {
+            K2 key = (lane >= t && lane < k) ? k2_make(fabs((double)A[lane * LD + t]), lane, 0) : k2_none();
+            key = wave_argmax(key);
+            const double pav = k2_val(key);
+            if (pav == 0.0) {
+                ok = 0;
+                break;
+            }
+            minpiv = fmin(minpiv, pav);
+            const int p = (int)k2_row(key);
+            const LT piv = A[p * LD + t];
+            if (lane == t) dreg = piv;
+            // multiplier of the row that lands in position s after the interchange
+            const int srow = lane < k ? (lane == p ? t : lane) : t;
+            const LT lm = A[srow * LD + t] / piv;
+            const int wl = k - t - 1;
+            const int w = wl + nr;
+            int col[NB];
+            bool act[NB];
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const int cc = lane + 64 * jb;
+                act[jb] = cc < w;
+                col[jb] = act[jb] ? (cc < wl ? t + 1 + cc : rhs0 + cc - wl) : t;
+            }
+            wave_lds_sync();
+            // interchange rows t and p in the columns still in use; keep the new row t
+            LT prow[NB];
+#pragma unroll
+            for (int jb = 0; jb < NB; ++jb) {
+                const LT a = A[t * LD + col[jb]];
+                const LT b = A[p * LD + col[jb]];
+                prow[jb] = act[jb] ? b : (LT)0;
+                A[t * LD + col[jb]] = act[jb] ? b : a;
+                A[p * LD + col[jb]] = act[jb] ? a : b;
+            }
+            wave_lds_sync();
+            // rows below the pivot, four at a time (all loads before the stores)
+            int s2 = t + 1;
+            for (; s2 + 4 <= k; s2 += 4) {
+                LT f[4], v[4][NB];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    f[i] = readlane_t(lm, s2 + i);
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb) v[i][jb] = A[(s2 + i) * LD + col[jb]];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb) A[(s2 + i) * LD + col[jb]] = v[i][jb] - f[i] * prow[jb];
+            }
+            for (; s2 < k; ++s2) {
+                const LT f = readlane_t(lm, s2);
+#pragma unroll
+                for (int jb = 0; jb < NB; ++jb) A[s2 * LD + col[jb]] = A[s2 * LD + col[jb]] - f * prow[jb];
+            }
+            wave_lds_sync();
+        }
+        if (ok) {
+            for (int t = k - 1; t >= 0; --t) {
+                const LT d = readlane_t(dreg, t);
+                const LT u = A[(lane < t ? lane : t) * LD + t];  // column t of U above the diagonal
+                int col[NB];
+                LT x[NB];
+#pragma unroll
+                for (int jb = 0; jb < NB; ++jb) {
+                    const int c = lane + 64 * jb;
+                    col[jb] = c < nr ? rhs0 + c : t;
+                    x[jb] = A[t * LD + col[jb]] / d;
+                    A[t * LD + col[jb]] = x[jb];
+                }
+                int s2 = 0;
+                for (; s2 + 4 <= t; s2 += 4) {
+                    LT f[4], v[4][NB];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        f[i] = readlane_t(u, s2 + i);
+#pragma unroll
+                        for (int jb = 0; jb < NB; ++jb) v[i][jb] = A[(s2 + i) * LD + col[jb]];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int jb = 0; jb < NB; ++jb) A[(s2 + i) * LD + col[jb]] = v[i][jb] - f[i] * x[jb];
+                }
+                for (; s2 < t; ++s2) {
+                    const LT f = readlane_t(u, s2);
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb) A[s2 * LD + col[jb]] = A[s2 * LD + col[jb]] - f * x[jb];
+                }
+                wave_lds_sync();
+            }
+        }
+        if (lane == 0) {
+            sm.ok = ok;
+            sm.minpiv = minpiv;
+        }
+    }
+}
+
 template <typename T, int KMAX, typename LT, int LD, int NB>
 DI void lu_aug_solve(LT* A, int k, int rhs0, int nr, Smem<T, KMAX>& sm)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (threadIdx.x == 0) {
-        sm.ok = 1;
-        sm.minpiv = INFINITY;
-    }
-    for (int t = 0; t < k; ++t) {
-        if (threadIdx.x < 64) {
-            const int s = t + threadIdx.x;
-            K2 key = s < k ? k2_make(fabs((double)A[s * LD + t]), s, 0) : k2_none();
-            key = wave_argmax(key);
-            if (threadIdx.x == 0) {
-                const double pav = k2_val(key);
-                sm.pivp = (int)k2_row(key);
-                if (pav == 0.0) sm.ok = 0;
-                sm.minpiv = fmin(sm.minpiv, pav);
-            }
-        }
-        __syncthreads();
-        if (!sm.ok) return;
-        const int p = sm.pivp;
-        const LT piv = A[p * LD + t];
-        const int wl = k - t - 1;  // left columns t+1 .. k-1
-        const int w = wl + nr;
-        // multipliers from the unswapped column t; interchange rows t and p
-        // in the columns still to be used
-        for (int s2 = t + 1 + threadIdx.x; s2 < k; s2 += NT)
-            sm.fcol[s2] = (double)(A[(s2 == p ? t : s2) * LD + t] / piv);
-        if (threadIdx.x == 0) sm.diag[t] = (double)piv;
-        if (p != t)
-            for (int cc = threadIdx.x; cc < w; cc += NT) {
-                const int c = cc < wl ? t + 1 + cc : rhs0 + cc - wl;
-                const LT a = A[t * LD + c];
-                A[t * LD + c] = A[p * LD + c];
-                A[p * LD + c] = a;
-            }
-        __syncthreads();
-        // rows below the pivot, this wavefront's rows, NB column blocks of 64
-        LT pv[NB];
-        int col[NB];
-#pragma unroll
-        for (int jb = 0; jb < NB; ++jb) {
-            const int cc = lane + 64 * jb;
-            col[jb] = cc < w ? (cc < wl ? t + 1 + cc : rhs0 + cc - wl) : -1;
-            pv[jb] = col[jb] >= 0 ? A[t * LD + col[jb]] : (LT)0;
-        }
-        for (int sb = t + 1 + wv; sb < k; sb += NWAVE * 8) {
-            LT v[8][NB], f[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int s2 = sb + i * NWAVE;
-                if (s2 < k) {
-                    f[i] = (LT)sm.fcol[s2];
-#pragma unroll
-                    for (int jb = 0; jb < NB; ++jb)
-                        if (col[jb] >= 0) v[i][jb] = A[s2 * LD + col[jb]];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int s2 = sb + i * NWAVE;
-                if (s2 < k) {
-#pragma unroll
-                    for (int jb = 0; jb < NB; ++jb)
-                        if (col[jb] >= 0) A[s2 * LD + col[jb]] = v[i][jb] - f[i] * pv[jb];
-                }
-            }
-        }
-        __syncthreads();
-    }
-    for (int t = k - 1; t >= 0; --t) {
-        const LT d = (LT)sm.diag[t];
-        for (int c = threadIdx.x; c < nr; c += NT) A[t * LD + rhs0 + c] /= d;
-        for (int s2 = threadIdx.x; s2 < t; s2 += NT) sm.fcol[s2] = (double)A[s2 * LD + t];
-        __syncthreads();
-        LT xv[NB];
-        int col[NB];
-#pragma unroll
-        for (int jb = 0; jb < NB; ++jb) {
-            const int c = lane + 64 * jb;
-            col[jb] = c < nr ? rhs0 + c : -1;
-            xv[jb] = col[jb] >= 0 ? A[t * LD + col[jb]] : (LT)0;
-        }
-        for (int sb = wv; sb < t; sb += NWAVE * 8) {
-            LT v[8][NB], f[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int s2 = sb + i * NWAVE;
-                if (s2 < t) {
-                    f[i] = (LT)sm.fcol[s2];
-#pragma unroll
-                    for (int jb = 0; jb < NB; ++jb)
-                        if (col[jb] >= 0) v[i][jb] = A[s2 * LD + col[jb]];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int s2 = sb + i * NWAVE;
-                if (s2 < t) {
-#pragma unroll
-                    for (int jb = 0; jb < NB; ++jb)
-                        if (col[jb] >= 0) A[s2 * LD + col[jb]] = v[i][jb] - f[i] * xv[jb];
-                }
-            }
-        }
-        __syncthreads();
-    }
+    __syncthreads();
+    if (threadIdx.x < 64) lu_aug_wave0<T, KMAX, LT, LD, NB>(A, k, rhs0, nr, sm);
+    __syncthreads();
 }
 
 // ----------------------------------------------------------------------------
@@ -582,54 +639,46 @@ DI Rows<T> slice_of(const TaskDesc& td, const Team& tm, int transpose, int64_t& 
     return rw;
 }
 
-// Warm start: partial-pivot LU of M = Chat^T (Chat = strip[X, :]) solved
-// against the identity, giving M^{-1} in the right half of AUG (so that
-// B = C Chat^{-1} = C (M^{-1})^T).  Returns 1 unless a pivot was exactly 0;
-// the smallest pivot modulus is left in sm.minpiv.
+// Warm start: M = Chat^T (Chat = strip[X, :]) beside the identity in AUG;
+// the partial-pivot LU solve then leaves M^{-1} in the right half (so that
+// B = C Chat^{-1} = C (M^{-1})^T).
 template <typename T, int KMAX>
-NOINL int warm_phase(const TaskDesc& td, Team& tio, int transpose)
+DI void warm_load(const TaskDesc& td, Smem<T, KMAX>& sm, int transpose)
 {
-    Team tm = tio;
-    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
     const int k = sm.k;
     const int64_t* F = transpose ? sm.I : sm.J;
     const int64_t* X = transpose ? sm.J : sm.I;
     constexpr int LD = 2 * KMAX;
     T* AUG = (T*)sm.AUG;
-    {
-        // M[c][s] = strip(X[s], c); all loads issued before the stores
-        constexpr int PER = (KMAX * KMAX + NT - 1) / NT;
-        T mv[PER];
+    // M[c][s] = strip(X[s], c); all loads issued before the stores
+    constexpr int PER = (KMAX * KMAX + NT - 1) / NT;
+    T mv[PER];
 #pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = threadIdx.x + i * NT;
-            if (e < k * k) {
-                const int c = e / k, s2 = e % k;
-                mv[i] = transpose ? entry_t<T>(td.src, F[c], X[s2]) : entry_t<T>(td.src, X[s2], F[c]);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = threadIdx.x + i * NT;
-            if (e < k * k) {
-                const int c = e / k, s2 = e % k;
-                AUG[c * LD + s2] = mv[i];
-                AUG[c * LD + KMAX + s2] = (T)(c == s2 ? 1 : 0);
-            }
+    for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (e < k * k) {
+            const int c = e / k, s2 = e % k;
+            mv[i] = transpose ? entry_t<T>(td.src, F[c], X[s2]) : entry_t<T>(td.src, X[s2], F[c]);
         }
     }
-    __syncthreads();
-    lu_aug_solve<T, KMAX, T, LD, (2 * KMAX + 63) / 64>(AUG, k, KMAX, k, sm);
-    const int ok = sm.ok;
-    trace_ev(tm, EV_WARM_LU, ok);
-    tio = tm;
-    return ok;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int e = threadIdx.x + i * NT;
+        if (e < k * k) {
+            const int c = e / k, s2 = e % k;
+            AUG[c * LD + s2] = mv[i];
+            AUG[c * LD + KMAX + s2] = (T)(c == s2 ? 1 : 0);
+        }
+    }
 }
 
 // Gather this workgroup's rows of the strip and return the team-wide max
-// |entry| (+inf when an entry is not finite, -1 when the team failed).
+// |entry| (+inf when an entry is not finite, -1 when the team failed).  With
+// warm, wavefront 0 meanwhile solves the warm-start system (it depends on
+// the index sets only), leaving sm.ok and sm.minpiv, while the other
+// wavefronts gather.
 template <typename T, int KMAX, bool LDSB>
-NOINL double gather_phase(const TaskDesc& td, Team& tio, int transpose)
+NOINL double gather_phase(const TaskDesc& td, Team& tio, int transpose, int warm)
 {
     Team tm = tio;
     Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
@@ -637,14 +686,20 @@ NOINL double gather_phase(const TaskDesc& td, Team& tio, int transpose)
     const int64_t* F = transpose ? sm.I : sm.J;
     int64_t R;
     const Rows<T> rw = slice_of<T, KMAX, LDSB>(td, tm, transpose, R);
-    if (td.src.kind != 0) {
-        if (threadIdx.x < k)
-            sm.pts[threadIdx.x] = transpose ? load_elem(td.src.x, td.src.dtype, F[threadIdx.x])
-                                            : load_elem(td.src.y, td.src.dtype, F[threadIdx.x]);
-        __syncthreads();
+    if (td.src.kind != 0 && threadIdx.x < k)
+        sm.pts[threadIdx.x] = transpose ? load_elem(td.src.x, td.src.dtype, F[threadIdx.x])
+                                        : load_elem(td.src.y, td.src.dtype, F[threadIdx.x]);
+    if (warm) warm_load<T, KMAX>(td, sm, transpose);
+    __syncthreads();
+    double lmax = 0.0;
+    if (warm) {
+        if (threadIdx.x < 64) lu_aug_wave0<T, KMAX, T, 2 * KMAX, (2 * KMAX + 63) / 64>((T*)sm.AUG, k, KMAX, k, sm);
+        else lmax = gather_rows<T, KMAX>(td.src, transpose, sm, F, k, rw, threadIdx.x - 64, NT - 64);
+    } else {
+        lmax = gather_rows<T, KMAX>(td.src, transpose, sm, F, k, rw, threadIdx.x, NT);
     }
-    const double lmax = gather_rows<T, KMAX>(td.src, transpose, sm, F, k, rw);
     K2 km = block_argmax(k2_make(lmax, 0, 0), sm, tm);
+    trace_ev(tm, EV_WARM_LU, warm);
     km = team_argmax(tm, sm, km, 0, R);
     tio = tm;
     if (tm.failed) return -1.0;
@@ -921,11 +976,10 @@ DI void maxvol_step(const TaskDesc& td, Team& tm, int transpose)
     const double u = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
     trace_ev(tm, EV_STEP_BEGIN, transpose);
 
-    const int warm_ok = warm ? warm_phase<T, KMAX>(td, tm, transpose) : 0;
-    const double minpiv = sm.minpiv;
-
-    const double cmax = gather_phase<T, KMAX, LDSB>(td, tm, transpose);
+    const double cmax = gather_phase<T, KMAX, LDSB>(td, tm, transpose, warm ? 1 : 0);
     if (tm.failed) return;
+    const int warm_ok = warm ? sm.ok : 0;
+    const double minpiv = sm.minpiv;
     if (threadIdx.x == 0) sm.entries_read += M * k;
     if (isinf(cmax)) {
         if (threadIdx.x == 0) { sm.status = -6; sm.phase = PH_DONE; }
@@ -1009,18 +1063,19 @@ DI double block_sum(double v, Smem<T, KMAX>& sm)
 // nucleus U = A[I,J]^{-1} and the sampled residual (leader workgroup only)
 // ----------------------------------------------------------------------------
 
-template <typename T, int KMAX>
-NOINL void final_leader(const TaskDesc& td, Team& tio, int lds_b_bytes)
+// FLDS: the work matrices fit the workgroup's LDS (else they live in the
+// problem's global work buffer); a compile-time choice keeps LDS accesses
+// ds_* instructions.
+template <typename T, int KMAX, bool FLDS>
+DI void final_core(const TaskDesc& td, Team& tio)
 {
     Team tm = tio;
     Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
-    T* Blds = blds_ptr<T, KMAX>();
     const int k = sm.k;
     const int q = td.q, s = td.s;
     // F = [G | I | A[I,S]] (row stride LDF; s <= 64), then A[Q,J] and A[Q,S]
     constexpr int LDF = 2 * KMAX + 64;
-    const int64_t need = (int64_t)KMAX * LDF + (int64_t)q * k + (int64_t)q * s;
-    double* Fm = need * 8 <= lds_b_bytes ? (double*)Blds : td.work;
+    double* Fm = FLDS ? (double*)blds_ptr<T, KMAX>() : td.work;
     double* AQJ = Fm + (int64_t)KMAX * LDF;
     double* E = AQJ + (int64_t)q * k;
     for (int e = threadIdx.x; e < k * k; e += NT) {
@@ -1121,6 +1176,15 @@ NOINL void final_leader(const TaskDesc& td, Team& tio, int lds_b_bytes)
     }
     __syncthreads();
     tio = tm;
+}
+
+template <typename T, int KMAX>
+NOINL void final_leader(const TaskDesc& td, Team& tio, int lds_b_bytes)
+{
+    constexpr int LDF = 2 * KMAX + 64;
+    const int64_t need = (int64_t)KMAX * LDF + (int64_t)td.q * smem_ref<T, KMAX>().k + (int64_t)td.q * td.s;
+    if (need * 8 <= lds_b_bytes) final_core<T, KMAX, true>(td, tio);
+    else final_core<T, KMAX, false>(td, tio);
 }
 
 // ----------------------------------------------------------------------------
@@ -1270,6 +1334,7 @@ __global__ __launch_bounds__(NT) void engine_kernel(EngineArgs ea)
     tm.size = ti.size;
     tm.rank = blockIdx.x - ti.first_wg;
     tm.epoch = 0;
+    tm.xepoch = 0;
     tm.failed = false;
     tm.tog = 0;
     tm.err = ea.error_flag;

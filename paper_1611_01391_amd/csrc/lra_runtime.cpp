@@ -217,12 +217,26 @@ extern "C" lra_status lra_create(lra_ctx** out, void* stream, size_t budget)
     if (const char* t = std::getenv("LRA_TRACE")) c->trace = std::atoi(t) != 0;
     // LDS for strip rows: all the device leaves per workgroup after the fixed
     // part of each kernel variant (LRA_LDS_B_BYTES caps it)
-    c->lds_cap = std::min(c->max_lds, 160 * 1024);
+    int static_lds = 0;
+    for (int p = 0; p < 2; ++p)
+        for (int km : {8, 16, 32, 64}) {
+            hipFuncAttributes fa;
+            e = hipFuncGetAttributes(&fa, engine_kernel_ptr(p, km));
+            if (e != hipSuccess) { delete c; return hip_fail(e, "hipFuncGetAttributes"); }
+            static_lds = std::max(static_lds, (int)fa.sharedSizeBytes);
+        }
+    c->lds_cap = (std::min(c->max_lds, 160 * 1024) - static_lds) & ~255;
     if (const char* t = std::getenv("LRA_LDS_B_BYTES")) c->lds_b_bytes = std::atoi(t);
     for (int p = 0; p < 2; ++p)
-        for (int km : {8, 16, 32, 64})
-            (void)hipFuncSetAttribute(engine_kernel_ptr(p, km), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      c->lds_cap);
+        for (int km : {8, 16, 32, 64}) {
+            e = hipFuncSetAttribute(engine_kernel_ptr(p, km), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    c->lds_cap);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                delete c;
+                return hip_fail(e, "hipFuncSetAttribute");
+            }
+        }
     LRA_LOG(1, "device %d: %d CUs, %d B LDS/block, wall clock %lld kHz", c->device, c->num_cu, c->max_lds,
             (long long)c->wall_rate_khz);
     *out = c;
@@ -251,6 +265,7 @@ struct Prob {
     int q, s;
     std::vector<int64_t> cand, Q, S;
     int team = 1;
+    bool team_fixed = false;  // chosen by the caller: never resized
     bool need_strip = false;
     void* C_out = nullptr;
     void* R_out = nullptr;
@@ -440,6 +455,9 @@ struct Plan {
     int max_team = 1;
 };
 
+// Work of a problem for planning: strip entries over all sweeps.
+static double prob_cost(const Prob& p) { return (double)(p.m + p.n) * p.kcap * p.sweeps; }
+
 static int pow2_ceil(int v)
 {
     int p = 1;
@@ -456,9 +474,7 @@ static Plan plan_teams(const std::vector<Prob*>& probs, int max_wgs)
     Plan pl;
     std::map<int, std::vector<int32_t>> cls;
     for (int i = 0; i < (int)probs.size(); ++i) cls[probs[i]->team].push_back(i);
-    auto cost_of = [&](int i) {
-        return (double)(probs[i]->m + probs[i]->n) * probs[i]->kcap * probs[i]->sweeps;
-    };
+    auto cost_of = [&](int i) { return prob_cost(*probs[i]); };
     std::vector<int> size, nteam, nitems;
     std::vector<double> cost;
     int reserved = 0;
@@ -523,6 +539,30 @@ struct LaunchPlan {
     Plan pl;
 };
 
+static int pow2_floor(int v)
+{
+    int p = 1;
+    while (2 * p <= v) p <<= 1;
+    return p;
+}
+
+// Throughput sizing for problems sharing a launch: each team gets about its
+// problem's share of the grid's workgroups (a power of two, at least one),
+// never more than the latency-optimal size the problem came with, so that
+// large and small problems finish together.
+static void share_teams(std::vector<Prob*>& probs, int max_wgs)
+{
+    if (probs.size() < 2) return;
+    double tot = 0.0;
+    for (Prob* p : probs) tot += prob_cost(*p);
+    for (Prob* p : probs) {
+        if (p->team_fixed) continue;
+        const double share = (double)max_wgs * prob_cost(*p) / std::max(tot, 1.0);
+        const int t = pow2_floor((int)std::max(1.0, std::min(share, (double)max_wgs)));
+        p->team = std::max(1, std::min(p->team, t));
+    }
+}
+
 // Fit the problems' teams to the co-resident grid of the (precision, KMAX)
 // kernel and plan the queues.  With fixed_strip the problems already own a
 // global strip region (serving), so any team size is safe; otherwise each
@@ -538,6 +578,7 @@ static lra_status plan_launch(lra_ctx* ctx, std::vector<Prob*>& probs, int prec6
     if (occ < 1) return LRA_EDEVICE;
     lp.max_wgs = occ * ctx->num_cu;
     for (Prob* p : probs) p->team = std::max(1, std::min(p->team, lp.max_wgs));
+    share_teams(probs, lp.max_wgs);
     // every size class holds at least one team: halve the largest sizes until
     // the classes fit the grid together
     for (;;) {
@@ -912,6 +953,7 @@ extern "C" lra_status lra_ca_cur_batched(lra_ctx* ctx, const lra_block* blocks, 
         // power-of-two team sizes keep the number of size classes small
         probs[b].team = o.team_wgs > 0 ? std::min(o.team_wgs, NT)
                                        : std::min(NT, pow2_ceil(auto_team(ctx, probs[b], prec64)));
+        probs[b].team_fixed = o.team_wgs > 0;
         probs[b].C_out = results[b].C_out;
         probs[b].R_out = results[b].R_out;
         rp[b] = &results[b];
@@ -1328,6 +1370,7 @@ extern "C" lra_status lra_submit(lra_ctx* ctx, const lra_request* req, uint64_t*
     q->prec64 = req->opts.precision == LRA_PREC_FP64;
     q->team = req->opts.team_wgs > 0 ? std::min(req->opts.team_wgs, NT)
                                      : std::min(NT, pow2_ceil(auto_team(ctx, q->p, q->prec64)));
+    q->p.team_fixed = req->opts.team_wgs > 0;
     q->kmx = kmax_bucket(q->p.kcap);
     q->p.need_strip = true;
     q->p.C_out = req->result->C_out;
