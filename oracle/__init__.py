@@ -82,10 +82,6 @@ def lib():
             f.restype = C.c_int
             f.argtypes = [P, C.c_int64, C.c_int, P, C.c_int, C.c_double, C.c_int,
                           C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(Trace)]
-            f = getattr(L, "oracle_maxvol_carried_" + sfx)
-            f.restype = C.c_int
-            f.argtypes = [P, C.c_int64, C.c_int, P, P, C.c_double, C.c_int, C.POINTER(C.c_int),
-                          C.POINTER(Trace)]
         L.oracle_nucleus.restype = C.c_int
         L.oracle_nucleus.argtypes = [C.POINTER(Source), P, P, C.c_int, P, P, C.POINTER(C.c_double)]
         L.oracle_residual.restype = None
@@ -200,22 +196,6 @@ def maxvol(strip: np.ndarray, tau: float = 0.01, init=None, max_swaps: int = 0,
     ke = keff.value
     return dict(I=I[:ke].copy(), B=B[:, :ke].copy(), swaps=sw, k_eff=ke,
                 capped=bool(capped.value), trace=tr)
-
-
-def maxvol_carried(strip: np.ndarray, init, cinv: np.ndarray, tau: float = 0.01,
-                   max_swaps: int = 0, precision: str = "f64"):
-    """maxvol from rows `init` with the carried inverse cinv = strip[init,:]^{-1}.
-    Returns dict(I, B, Cinv, swaps, capped)."""
-    dt = np.float64 if precision == "f64" else np.float32
-    m, k = strip.shape
-    B = np.asfortranarray(strip.astype(dt))
-    I = np.ascontiguousarray(np.asarray(init, dtype=np.int64))
-    Ci = np.ascontiguousarray(np.asarray(cinv, dtype=dt))
-    capped = C.c_int(0)
-    tr = _new_trace()
-    f = lib().oracle_maxvol_carried_f64 if precision == "f64" else lib().oracle_maxvol_carried_f32
-    sw = f(_ptr(B), m, k, _ptr(I), _ptr(Ci), float(tau), int(max_swaps), C.byref(capped), C.byref(tr))
-    return dict(I=I.copy(), B=B.copy(), Cinv=Ci.copy(), swaps=sw, capped=bool(capped.value), trace=tr)
 
 
 def nucleus(src: HostSource, I, J):

@@ -97,23 +97,13 @@ int oracle_gepp_basis_f64(double* C, int64_t m, int k, int64_t* I, oracle_trace*
 int oracle_gepp_basis_f32(float* C, int64_t m, int k, int64_t* I, oracle_trace* tr);
 
 /* maxvol on the m x k column-major strip C (overwritten by the final basis).
- * If have_init, I holds k distinct rows to warm-start from (LU solve with
- * C[I,:]^T, or the strip LU when a pivot is under the rank threshold); else
- * the start is the partial-pivot LU.  Returns the number of swaps (>= 0), or a negative
+ * If have_init, I holds k distinct rows to warm-start from; else the start is
+ * the partial-pivot LU.  Returns the number of swaps (>= 0), or a negative
  * status; *k_eff receives the rank actually used. */
 int oracle_maxvol_f64(double* C, int64_t m, int k, int64_t* I, int have_init,
                       double tau, int max_swaps, int* k_eff, int* capped, oracle_trace* tr);
 int oracle_maxvol_f32(float* C, int64_t m, int k, int64_t* I, int have_init,
                       double tau, int max_swaps, int* k_eff, int* capped, oracle_trace* tr);
-
-/* maxvol warm-started from a carried inverse: Cinv (k x k row-major) holds
- * C[I,:]^{-1} on entry; B = C * Cinv, and every swap updates Cinv by the
- * same rank-one form as B, so on return Cinv = C[I_final,:]^{-1}.  Returns
- * the number of swaps. */
-int oracle_maxvol_carried_f64(double* C, int64_t m, int k, int64_t* I, double* Cinv, double tau,
-                              int max_swaps, int* capped, oracle_trace* tr);
-int oracle_maxvol_carried_f32(float* C, int64_t m, int k, int64_t* I, float* Cinv, double tau,
-                              int max_swaps, int* capped, oracle_trace* tr);
 
 /* Nucleus: G = A[I,J] (binary64), U = G^{-1} via partial-pivot LU.
  * G, U: k x k row-major.  Returns 0, or -2 if G is exactly singular. */
