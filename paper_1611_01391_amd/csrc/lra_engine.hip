@@ -242,14 +242,17 @@ DI void team_barrier(Team& tm, Smem<T, KMAX>& sm)
         const uint32_t target = (tm.epoch + 1) * (uint32_t)tm.size;
         const int64_t t0 = wall_clock64();
         int bad = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, AGENT) < target) {
+        // relaxed polling, one acquire fence once the count is reached (an
+        // acquire load per iteration would invalidate the caches each time)
+        for (uint32_t spins = 1; __hip_atomic_load(ctr, __ATOMIC_RELAXED, AGENT) < target; ++spins) {
             __builtin_amdgcn_s_sleep(1);
-            if (wall_clock64() - t0 > tm.timeout) {
+            if ((spins & 63) == 0 && wall_clock64() - t0 > tm.timeout) {
                 atomicOr(tm.err, 1u);
                 bad = 1;
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         sm.flag = bad;
     }
     __syncthreads();
@@ -289,14 +292,16 @@ DI K2 team_argmax(Team& tm, Smem<T, KMAX>& sm, const K2& mine, int n, int64_t ro
         const uint8_t* sp = slot_ptr(tm, par, threadIdx.x);
         const int64_t t0 = wall_clock64();
         bool bad = false;
-        while (__hip_atomic_load((const uint32_t*)(sp + 16), __ATOMIC_ACQUIRE, AGENT) != stamp) {
+        for (uint32_t spins = 1; __hip_atomic_load((const uint32_t*)(sp + 16), __ATOMIC_RELAXED, AGENT) != stamp;
+             ++spins) {
             __builtin_amdgcn_s_sleep(1);
-            if (wall_clock64() - t0 > tm.timeout) {
+            if ((spins & 63) == 0 && wall_clock64() - t0 > tm.timeout) {
                 atomicOr(tm.err, 1u);
                 bad = true;
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (bad) {
             o = K2{~0ull, ~0ull};
         } else {
