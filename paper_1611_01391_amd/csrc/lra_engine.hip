@@ -232,8 +232,9 @@ DI uint8_t* slot_ptr(const Team& tm, int parity, int wg)
     return tm.ctl + CTL_HDR + (int64_t)(parity * tm.size + wg) * SLOT_STRIDE;
 }
 
-template <typename T, int KMAX>
-DI void team_barrier(Team& tm, Smem<T, KMAX>& sm)
+DI int32_t* lds_flag();
+
+DI void team_barrier(Team& tm)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -253,11 +254,11 @@ DI void team_barrier(Team& tm, Smem<T, KMAX>& sm)
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        sm.flag = bad;
+        *lds_flag() = bad;
     }
     __syncthreads();
     tm.epoch++;
-    if (sm.flag) tm.failed = true;
+    if (*lds_flag()) tm.failed = true;
 }
 
 // Team-wide argmax: publish this workgroup's best key and its candidate row
@@ -616,11 +617,27 @@ DI void basis_product(const Rows<T>& rw, int kd, const T* W, int wsd, int wsc)
 
 extern __shared__ __align__(16) unsigned char lra_smem[];
 
-template <typename T, int KMAX>
-DI Smem<T, KMAX>& smem_ref() { return *reinterpret_cast<Smem<T, KMAX>*>(lra_smem); }
+// Dynamic LDS: a small header shared by every variant (the fetched task and
+// the team-barrier flag), then the variant's Smem, then its strip rows.
+constexpr int LDS_HDR = 64;
+
+DI int32_t* lds_fetch() { return reinterpret_cast<int32_t*>(lra_smem); }
+DI int32_t* lds_flag() { return reinterpret_cast<int32_t*>(lra_smem) + 1; }
 
 template <typename T, int KMAX>
-DI T* blds_ptr() { return reinterpret_cast<T*>(lra_smem + ((sizeof(Smem<T, KMAX>) + 255) & ~(size_t)255)); }
+DI Smem<T, KMAX>& smem_ref() { return *reinterpret_cast<Smem<T, KMAX>*>(lra_smem + LDS_HDR); }
+
+template <typename T, int KMAX>
+DI T* blds_ptr()
+{
+    return reinterpret_cast<T*>(lra_smem + LDS_HDR + ((sizeof(Smem<T, KMAX>) + 255) & ~(size_t)255));
+}
+
+template <typename T, int KMAX>
+constexpr int variant_of()
+{
+    return 4 * (sizeof(T) == 8 ? 1 : 0) + (KMAX <= 8 ? 0 : KMAX <= 16 ? 1 : KMAX <= 32 ? 2 : 3);
+}
 
 #define NOINL __device__ __noinline__
 
@@ -1268,8 +1285,10 @@ NOINL void store_state(const TaskDesc& td, Smem<T, KMAX>& sm)
 
 // Run one problem for up to `budget` phases.
 template <typename T, int KMAX>
-DI void run_task(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, const EngineArgs& ea, T* Blds)
+DI void run_task(const TaskDesc& td, Team& tm, const EngineArgs& ea)
 {
+    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
+    const int lds_b = ea.lds_b[variant_of<T, KMAX>()];
     load_state(td, sm);
     int budget = ea.phase_budget;
     while (sm.phase != PH_DONE && budget > 0) {
@@ -1285,7 +1304,7 @@ DI void run_task(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, const EngineAr
                 sm.k_sweep_start = sm.k;
             }
             __syncthreads();
-            maxvol_dispatch<T, KMAX>(td, tm, 0, ea.lds_b_bytes);
+            maxvol_dispatch<T, KMAX>(td, tm, 0, lds_b);
             if (tm.failed) return;
             if (threadIdx.x == 0 && sm.phase != PH_DONE) {
                 sm.have_I = 1;
@@ -1293,7 +1312,7 @@ DI void run_task(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, const EngineAr
             }
             __syncthreads();
         } else if (ph == PH_ROW) {
-            maxvol_dispatch<T, KMAX>(td, tm, 1, ea.lds_b_bytes);
+            maxvol_dispatch<T, KMAX>(td, tm, 1, lds_b);
             if (tm.failed) return;
             if (threadIdx.x == 0 && sm.phase != PH_DONE) {
                 sm.sweeps_done += 1;
@@ -1311,12 +1330,12 @@ DI void run_task(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, const EngineAr
         } else {  // PH_FINAL
             trace_ev(tm, EV_FINAL_BEGIN, 0);
             write_factors<T, KMAX>(td, sm, tm);
-            if (tm.rank == 0) final_leader<T, KMAX>(td, tm, ea.lds_b_bytes);
+            if (tm.rank == 0) final_leader<T, KMAX>(td, tm, lds_b);
             trace_ev(tm, EV_FINAL_END, 0);
             if (tm.size > 1) {
                 // the leader's decision reaches the team through global memory
                 if (tm.rank == 0) store_state(td, sm);
-                team_barrier(tm, sm);
+                team_barrier(tm);
                 if (tm.failed) return;
                 if (tm.rank != 0) load_state(td, sm);
             }
@@ -1327,11 +1346,13 @@ DI void run_task(const TaskDesc& td, Smem<T, KMAX>& sm, Team& tm, const EngineAr
     }
 }
 
-template <typename T, int KMAX>
-__global__ __launch_bounds__(NT) void engine_kernel(EngineArgs ea)
+// The persistent loop of a workgroup: its team pulls task indices from the
+// team's queue (the leader fetches, the team sees the index through the
+// control block) and runs each for up to phase_budget phases.  RUN(td, tm)
+// runs one task.
+template <typename RUN>
+DI void engine_loop(const EngineArgs& ea, RUN run)
 {
-    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
-    T* Blds = blds_ptr<T, KMAX>();
     const int team = ea.wg_team[blockIdx.x];
     const TeamInfo ti = ea.teams[team];
     Team tm;
@@ -1352,24 +1373,48 @@ __global__ __launch_bounds__(NT) void engine_kernel(EngineArgs ea)
         int32_t* fetch = (int32_t*)(tm.ctl + 64) + par;
         if (threadIdx.x == 0 && tm.rank == 0) {
             const int idx = (int)atomicAdd(ea.queue_head + ti.queue, 1u);
-            sm.fetch = idx;
+            *lds_fetch() = idx;
             if (tm.size > 1) __hip_atomic_store(fetch, idx, __ATOMIC_RELAXED, AGENT);
         }
         if (tm.size > 1) {
-            team_barrier(tm, sm);
+            team_barrier(tm);
             if (tm.failed) return;
-            if (threadIdx.x == 0 && tm.rank != 0) sm.fetch = __hip_atomic_load(fetch, __ATOMIC_RELAXED, AGENT);
+            if (threadIdx.x == 0 && tm.rank != 0) *lds_fetch() = __hip_atomic_load(fetch, __ATOMIC_RELAXED, AGENT);
         }
         __syncthreads();
-        const int idx = sm.fetch;
+        const int idx = *lds_fetch();
         __syncthreads();
         if (idx >= ea.queue_len[ti.queue]) break;
         const int task = ea.queue_items[ea.queue_off[ti.queue] + idx];
         trace_ev(tm, EV_TASK_BEGIN, task);
-        run_task<T, KMAX>(ea.tasks[task], sm, tm, ea, Blds);
+        run(ea.tasks[task], tm);
         trace_ev(tm, EV_TASK_END, task);
         if (tm.failed) return;
     }
+}
+
+template <typename T, int KMAX>
+__global__ __launch_bounds__(NT) void engine_kernel(EngineArgs ea)
+{
+    engine_loop(ea, [&](const TaskDesc& td, Team& tm) { run_task<T, KMAX>(td, tm, ea); });
+}
+
+// Every variant in one launch (problems of mixed precision and rank bucket,
+// e.g. a serving tick): each task runs the variant it names.
+__global__ __launch_bounds__(NT) void engine_kernel_all(EngineArgs ea)
+{
+    engine_loop(ea, [&](const TaskDesc& td, Team& tm) {
+        switch (td.variant) {
+        case 0: run_task<float, 8>(td, tm, ea); break;
+        case 1: run_task<float, 16>(td, tm, ea); break;
+        case 2: run_task<float, 32>(td, tm, ea); break;
+        case 3: run_task<float, 64>(td, tm, ea); break;
+        case 4: run_task<double, 8>(td, tm, ea); break;
+        case 5: run_task<double, 16>(td, tm, ea); break;
+        case 6: run_task<double, 32>(td, tm, ea); break;
+        default: run_task<double, 64>(td, tm, ea); break;
+        }
+    });
 }
 
 // Zero-fill used instead of hipMemsetAsync (safe to record in a graph).
@@ -1391,7 +1436,7 @@ static const void* engine_fn()
 
 size_t engine_smem_fixed(int prec64, int kmax)
 {
-    auto sz = [](size_t s) { return (s + 255) & ~(size_t)255; };
+    auto sz = [](size_t s) { return LDS_HDR + ((s + 255) & ~(size_t)255); };
     if (prec64) {
         if (kmax <= 8) return sz(sizeof(Smem<double, 8>));
         if (kmax <= 16) return sz(sizeof(Smem<double, 16>));
@@ -1404,8 +1449,10 @@ size_t engine_smem_fixed(int prec64, int kmax)
     return sz(sizeof(Smem<float, 64>));
 }
 
+// kmax = 0 selects the all-variant kernel.
 const void* engine_kernel_ptr(int prec64, int kmax)
 {
+    if (kmax == 0) return reinterpret_cast<const void*>(&engine_kernel_all);
     if (prec64) {
         if (kmax <= 8) return engine_fn<double, 8>();
         if (kmax <= 16) return engine_fn<double, 16>();

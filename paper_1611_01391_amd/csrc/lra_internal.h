@@ -64,7 +64,15 @@ struct TaskDesc {
     void* C_out;       // optional: A[:,J], m x k column-major, strip precision
     void* R_out;       // optional: A[I,:], k x n row-major, strip precision
     TaskState* st;
+    int32_t variant;   // kernel variant: 4 * (binary64 strips) + log2(KMAX / 8)
+    int32_t pad_v;
 };
+
+constexpr int NVARIANT = 8;
+inline int variant_index(int prec64, int kmax)
+{
+    return 4 * (prec64 ? 1 : 0) + (kmax <= 8 ? 0 : kmax <= 16 ? 1 : kmax <= 32 ? 2 : 3);
+}
 
 struct TeamInfo {
     int32_t first_wg;
@@ -84,12 +92,11 @@ struct EngineArgs {
     uint8_t* team_ctl;            // per-team control block, zero at launch
     int64_t team_ctl_stride;
     int32_t phase_budget;         // phases per task per launch (large: run to completion)
-    int32_t lds_b_bytes;          // LDS bytes available for a workgroup's strip rows
+    int32_t lds_b[8];             // LDS bytes for a workgroup's strip rows, per variant
     uint32_t* error_flag;         // bit 0: a team barrier timed out
     int64_t timeout_ticks;        // in wall_clock64() ticks
     uint64_t* trace;              // optional event trace: [0] = count, then (event, clock) pairs
     int32_t trace_cap;            // pairs
-    int32_t pad2;
 };
 
 // Trace events (recorded by thread 0 of a team's first workgroup).

@@ -219,7 +219,7 @@ extern "C" lra_status lra_create(lra_ctx** out, void* stream, size_t budget)
     // part of each kernel variant (LRA_LDS_B_BYTES caps it)
     int static_lds = 0;
     for (int p = 0; p < 2; ++p)
-        for (int km : {8, 16, 32, 64}) {
+        for (int km : {0, 8, 16, 32, 64}) {
             hipFuncAttributes fa;
             e = hipFuncGetAttributes(&fa, engine_kernel_ptr(p, km));
             if (e != hipSuccess) { delete c; return hip_fail(e, "hipFuncGetAttributes"); }
@@ -228,7 +228,7 @@ extern "C" lra_status lra_create(lra_ctx** out, void* stream, size_t budget)
     c->lds_cap = (std::min(c->max_lds, 160 * 1024) - static_lds) & ~255;
     if (const char* t = std::getenv("LRA_LDS_B_BYTES")) c->lds_b_bytes = std::atoi(t);
     for (int p = 0; p < 2; ++p)
-        for (int km : {8, 16, 32, 64}) {
+        for (int km : {0, 8, 16, 32, 64}) {
             e = hipFuncSetAttribute(engine_kernel_ptr(p, km), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     c->lds_cap);
             if (e != hipSuccess) {
@@ -265,6 +265,7 @@ struct Prob {
     int q, s;
     std::vector<int64_t> cand, Q, S;
     int team = 1;
+    int prec64 = 1, kmx = 8;  // kernel variant the problem runs with
     bool team_fixed = false;  // chosen by the caller: never resized
     bool need_strip = false;
     void* C_out = nullptr;
@@ -418,6 +419,8 @@ static void fill_task(TaskDesc& td, const Prob& p, uint8_t* base, const ProbRegi
     td.C_out = p.C_out;
     td.R_out = p.R_out;
     td.st = (TaskState*)(base + r.st);
+    td.variant = variant_index(p.prec64, p.kmx);
+    td.pad_v = 0;
 }
 
 // Host image of the inputs (cand, Q, S) and of the initial state (st, I, J).
@@ -530,8 +533,9 @@ static Plan plan_teams(const std::vector<Prob*>& probs, int max_wgs)
 }
 
 struct LaunchPlan {
-    int kmx = 8;
-    int lds_b = 0;
+    int prec64 = 1;
+    int kmx = 8;          // 0: the all-variant kernel
+    int lds_b[NVARIANT] = {0};
     int max_wgs = 0;
     int grid = 0;
     size_t smem = 0;
@@ -564,15 +568,19 @@ static void share_teams(std::vector<Prob*>& probs, int max_wgs)
 }
 
 // Fit the problems' teams to the co-resident grid of the (precision, KMAX)
-// kernel and plan the queues.  With fixed_strip the problems already own a
-// global strip region (serving), so any team size is safe; otherwise each
-// problem's need for one is decided here.
+// kernel -- or of the all-variant kernel when kmx = 0, each problem then
+// running its own variant -- and plan the queues.  With fixed_strip the
+// problems already own a global strip region (serving), so any team size is
+// safe; otherwise each problem's need for one is decided here.
 static lra_status plan_launch(lra_ctx* ctx, std::vector<Prob*>& probs, int prec64, int kmx, bool fixed_strip,
                               LaunchPlan& lp)
 {
+    lp.prec64 = prec64;
     lp.kmx = kmx;
-    lp.lds_b = strip_lds(ctx, prec64, kmx);
-    lp.smem = engine_smem_fixed(prec64, kmx) + (size_t)lp.lds_b;
+    for (int p64 = 0; p64 < 2; ++p64)
+        for (int km : {8, 16, 32, 64}) lp.lds_b[variant_index(p64, km)] = strip_lds(ctx, p64, km);
+    lp.smem = kmx == 0 ? (size_t)ctx->lds_cap
+                       : engine_smem_fixed(prec64, kmx) + (size_t)lp.lds_b[variant_index(prec64, kmx)];
     int occ = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, engine_kernel_ptr(prec64, kmx), NT, lp.smem));
     if (occ < 1) return LRA_EDEVICE;
@@ -593,11 +601,10 @@ static lra_status plan_launch(lra_ctx* ctx, std::vector<Prob*>& probs, int prec6
         for (Prob* p : probs)
             if (p->team == big) p->team = std::max(1, big / 2);
     }
-    const int esz = prec64 ? 8 : 4;
     for (Prob* p : probs) {
         if (fixed_strip) continue;
         const int64_t R = (std::max(p->m, p->n) + p->team - 1) / p->team;
-        p->need_strip = R * p->kcap * esz > lp.lds_b;
+        p->need_strip = R * p->kcap * (p->prec64 ? 8 : 4) > lp.lds_b[variant_index(p->prec64, p->kmx)];
     }
     lp.pl = plan_teams(probs, lp.max_wgs);
     lp.grid = (int)lp.pl.wg_team.size();
@@ -688,17 +695,17 @@ static EngineArgs engine_args(lra_ctx* ctx, uint8_t* d, const CtlImage& c, const
     ea.team_ctl = d + c.ctl;
     ea.team_ctl_stride = c.ctl_stride;
     ea.phase_budget = phase_budget;
-    ea.lds_b_bytes = lp.lds_b;
+    for (int v = 0; v < NVARIANT; ++v) ea.lds_b[v] = lp.lds_b[v];
     ea.error_flag = err;
     ea.timeout_ticks = (int64_t)(ctx->timeout_s * (double)ctx->wall_rate_khz * 1000.0);
     ea.trace = trace;
     ea.trace_cap = trace_cap;
-    ea.pad2 = 0;
     return ea;
 }
 
-static lra_status launch(lra_ctx* ctx, int prec64, const LaunchPlan& lp, const EngineArgs& ea, hipStream_t stream)
+static lra_status launch(lra_ctx* ctx, const LaunchPlan& lp, const EngineArgs& ea, hipStream_t stream)
 {
+    const int prec64 = lp.prec64;
     LRA_LOG(2, "launch: grid %d, teams %zu (max %d), smem %zu, coop %d", lp.grid, lp.pl.teams.size(),
             lp.pl.max_team, lp.smem, (int)lp.coop);
     HIP_TRY(launch_engine(prec64, lp.kmx, lp.grid, lp.smem, lp.coop, ea, stream));
@@ -764,7 +771,11 @@ static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, 
     int kcap_all = 1;
     for (auto& p : probs) kcap_all = std::max(kcap_all, p.kcap);
     std::vector<Prob*> pp;
-    for (auto& p : probs) pp.push_back(&p);
+    for (auto& p : probs) {
+        p.prec64 = prec64;
+        p.kmx = kmax_bucket(kcap_all);
+        pp.push_back(&p);
+    }
     LaunchPlan lp;
     lra_status rs = plan_launch(ctx, pp, prec64, kmax_bucket(kcap_all), false, lp);
     if (rs != LRA_OK) return rs;
@@ -827,7 +838,7 @@ static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, 
     EngineArgs ea = engine_args(ctx, d, c, lp, phase_budget, (uint32_t*)(d + off_err),
                                 trace_cap ? (uint64_t*)(d + off_trace) : nullptr, trace_cap);
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev0, ctx->stream));
-    rs = launch(ctx, prec64, lp, ea, ctx->stream);
+    rs = launch(ctx, lp, ea, ctx->stream);
     if (rs != LRA_OK) return rs;
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev1, ctx->stream));
 
@@ -1152,9 +1163,15 @@ static lra_status serve_launch(lra_ctx* ctx)
     }
     if (s.active.empty()) return LRA_OK;
 
-    // groups by (precision, KMAX)
+    // one launch: the variant's own kernel when all requests share one, else
+    // the all-variant kernel (key (0, 0))
     std::map<std::pair<int, int>, std::vector<Request*>> groups;
     for (Request* q : s.active) groups[{q->prec64, q->kmx}].push_back(q);
+    if (groups.size() > 1) {
+        std::vector<Request*> all = s.active;
+        groups.clear();
+        groups[{0, 0}] = all;
+    }
     struct G {
         int prec64;
         LaunchPlan lp;
@@ -1225,7 +1242,7 @@ static lra_status serve_launch(lra_ctx* ctx)
         G& g = gs[gi];
         EngineArgs ea = engine_args(ctx, dc, g.c, g.lp, s.phases_per_tick, (uint32_t*)(dc + err_off + 8 * gi),
                                     nullptr, 0);
-        rs = launch(ctx, g.prec64, g.lp, ea, ctx->stream);
+        rs = launch(ctx, g.lp, ea, ctx->stream);
         if (rs != LRA_OK) return rs;
     }
     HIP_TRY(hipMemcpyAsync(h + tbl_off, da, (size_t)max_slot * sizeof(TaskState), hipMemcpyDeviceToHost,
@@ -1372,6 +1389,8 @@ extern "C" lra_status lra_submit(lra_ctx* ctx, const lra_request* req, uint64_t*
                                      : std::min(NT, pow2_ceil(auto_team(ctx, q->p, q->prec64)));
     q->p.team_fixed = req->opts.team_wgs > 0;
     q->kmx = kmax_bucket(q->p.kcap);
+    q->p.prec64 = q->prec64;
+    q->p.kmx = q->kmx;
     q->p.need_strip = true;
     q->p.C_out = req->result->C_out;
     q->p.R_out = req->result->R_out;
