@@ -526,6 +526,42 @@ DI void lu_aug_wave0(LT* A, int k, int rhs0, int nr, Smem<T, KMAX>& sm)
     }
 }
 
+// Inverse of the unit lower-triangular k x k matrix in columns [0, k) of A
+// (row stride LD; only the part below the diagonal is read) by elimination
+// on the right-hand sides [KMAX, KMAX + k), which hold the identity on entry
+// and the inverse on exit.  No pivot search: the multipliers of the strip's
+// partial-pivot LU are at most 1 in modulus, so partial pivoting would keep
+// every diagonal pivot, and the unit pivots make the divisions exact.
+// Wavefront 0 only; lane c owns right-hand-side column c (k <= 64).
+template <typename T, int KMAX, int LD>
+DI void unit_lower_inv_wave0(T* A, int k)
+{
+    const int lane = threadIdx.x;
+    const bool act = lane < k;
+    for (int t = 0; t + 1 < k; ++t) {
+        const T lm = A[(act ? lane : t) * LD + t];   // lane s: multiplier of row s
+        const int col = act ? KMAX + lane : t;       // inactive lanes touch dead column t
+        const T prow = act ? A[t * LD + col] : (T)0;
+        wave_lds_sync();
+        int s2 = t + 1;
+        for (; s2 + 4 <= k; s2 += 4) {
+            T f[4], v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                f[i] = readlane_t(lm, s2 + i);
+                v[i] = A[(s2 + i) * LD + col];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) A[(s2 + i) * LD + col] = v[i] - f[i] * prow;
+        }
+        for (; s2 < k; ++s2) {
+            const T f = readlane_t(lm, s2);
+            A[s2 * LD + col] = A[s2 * LD + col] - f * prow;
+        }
+        wave_lds_sync();
+    }
+}
+
 template <typename T, int KMAX, typename LT, int LD, int NB>
 DI void lu_aug_solve(LT* A, int k, int rhs0, int nr, Smem<T, KMAX>& sm)
 {
@@ -820,12 +856,12 @@ NOINL void basis_phase(const TaskDesc& td, Team& tio, int transpose, int started
         // W[d][c] = M^{-1}[c][d], in the right half of AUG
         basis_product<T, KMAX>(rw, keff, AUG + KMAX, 1, LD);
     } else {
-        // L1^{-1} from a solve against I (L1 needs no interchange: its
-        // multipliers are at most 1 in modulus), then L L1^{-1}
+        // L1^{-1} by unit-triangular elimination on I, then L L1^{-1}
         for (int e = threadIdx.x; e < keff * keff; e += NT)
             AUG[(e / keff) * LD + KMAX + e % keff] = (T)((e / keff) == (e % keff));
         __syncthreads();
-        lu_aug_solve<T, KMAX, T, LD, (2 * KMAX + 63) / 64>(AUG, keff, KMAX, keff, sm);
+        if (threadIdx.x < 64) unit_lower_inv_wave0<T, KMAX, LD>(AUG, keff);
+        __syncthreads();
         basis_product<T, KMAX>(rw, keff, AUG + KMAX, LD, 1);
     }
     __syncthreads();
@@ -1108,8 +1144,6 @@ DI void final_core(const TaskDesc& td, Team& tio)
         td.G[e] = v;
     }
     for (int e = threadIdx.x; e < k * s; e += NT) Fm[(e / s) * LDF + KMAX + k + e % s] = entry64(td.src, sm.I[e / s], td.S[e % s]);
-    for (int e = threadIdx.x; e < q * k; e += NT) AQJ[e] = entry64(td.src, td.Q[e / k], sm.J[e % k]);
-    for (int e = threadIdx.x; e < q * s; e += NT) E[e] = entry64(td.src, td.Q[e / s], td.S[e % s]);
     __threadfence_block();
     __syncthreads();
     // ||G||_1 before the factorisation overwrites G
@@ -1117,8 +1151,17 @@ DI void final_core(const TaskDesc& td, Team& tio)
     if (threadIdx.x < k)
         for (int a = 0; a < k; ++a) cg += fabs(Fm[a * LDF + threadIdx.x]);
     const double ng = k2_val(block_argmax(k2_make(cg, 0, 0), sm, tm));
-    // U = G^{-1} and W = G^{-1} A[I,S] by one partial-pivot LU solve
-    lu_aug_solve<T, KMAX, double, LDF, (2 * KMAX + 127) / 64>(Fm, k, KMAX, k + s, sm);
+    __syncthreads();
+    // U = G^{-1} and W = G^{-1} A[I,S] by one partial-pivot LU solve on
+    // wavefront 0, while the other wavefronts fetch A[Q,J] and A[Q,S]
+    if (threadIdx.x < 64) {
+        lu_aug_wave0<T, KMAX, double, LDF, (2 * KMAX + 127) / 64>(Fm, k, KMAX, k + s, sm);
+    } else {
+        for (int e = threadIdx.x - 64; e < q * k; e += NT - 64) AQJ[e] = entry64(td.src, td.Q[e / k], sm.J[e % k]);
+        for (int e = threadIdx.x - 64; e < q * s; e += NT - 64) E[e] = entry64(td.src, td.Q[e / s], td.S[e % s]);
+    }
+    __threadfence_block();
+    __syncthreads();
     if (!sm.ok) {
         if (threadIdx.x == 0) { sm.status = -2; sm.phase = PH_DONE; }
         __syncthreads();

@@ -63,18 +63,27 @@ uint64_t splitmix64(uint64_t seed, uint64_t ctr)
     return z ^ (z >> 31);
 }
 
-// cnt distinct indices in [0, n) in draw order (floor(v n / 2^64), repeats skipped).
+// cnt distinct indices in [0, n) in draw order (floor(v n / 2^64), repeats
+// skipped); an open-addressing set keeps the repeat test O(1).
 void draw_distinct(uint64_t seed, int64_t n, int64_t cnt, int64_t* out)
 {
-    std::vector<int64_t> seen;
+    size_t cap = 16;
+    while (cap < 2 * (size_t)cnt) cap <<= 1;
+    std::vector<int64_t> set(cap, -1);
     int64_t got = 0;
     for (uint64_t ctr = 0; got < cnt; ++ctr) {
         const uint64_t v = splitmix64(seed, ctr);
         const int64_t idx = (int64_t)(((unsigned __int128)v * (unsigned __int128)(uint64_t)n) >> 64);
+        size_t h = (size_t)(((uint64_t)idx * 0x9E3779B97F4A7C15ull) >> 20) & (cap - 1);
         bool dup = false;
-        for (int64_t e = 0; e < got; ++e)
-            if (out[e] == idx) { dup = true; break; }
-        if (!dup) out[got++] = idx;
+        while (set[h] >= 0) {
+            if (set[h] == idx) { dup = true; break; }
+            h = (h + 1) & (cap - 1);
+        }
+        if (!dup) {
+            set[h] = idx;
+            out[got++] = idx;
+        }
     }
 }
 
@@ -458,8 +467,27 @@ struct Plan {
     int max_team = 1;
 };
 
-// Work of a problem for planning: strip entries over all sweeps.
-static double prob_cost(const Prob& p) { return (double)(p.m + p.n) * p.kcap * p.sweeps; }
+// Work of a problem for planning: a C-A step costs about (rows) k^2 (the
+// first step's LU, the basis product, and about k swaps of rows x k updates),
+// over 2 sweeps' worth of steps.
+static double prob_cost(const Prob& p)
+{
+    return (double)(p.m + p.n) * (double)p.kcap * (double)p.kcap * (double)p.sweeps;
+}
+
+// A problem sharing a launch keeps at least ceil(rows / floor) workgroups
+// (at most 32): with one or two workgroups a long strip's first-step LU and
+// swap updates run from global memory on a single CU and become the launch's
+// critical path.  8192 rows measured best overall on the served stream and
+// the far-field blocks; LRA_SHARE_FLOOR_ROWS overrides it (0: no floor).
+static int64_t share_floor_rows()
+{
+    static int64_t v = [] {
+        const char* e = std::getenv("LRA_SHARE_FLOOR_ROWS");
+        return e ? (int64_t)std::atoll(e) : (int64_t)8192;
+    }();
+    return v;
+}
 
 static int pow2_ceil(int v)
 {
@@ -562,7 +590,12 @@ static void share_teams(std::vector<Prob*>& probs, int max_wgs)
     for (Prob* p : probs) {
         if (p->team_fixed) continue;
         const double share = (double)max_wgs * prob_cost(*p) / std::max(tot, 1.0);
-        const int t = pow2_floor((int)std::max(1.0, std::min(share, (double)max_wgs)));
+        int t = pow2_floor((int)std::max(1.0, std::min(share, (double)max_wgs)));
+        if (share_floor_rows() > 0) {
+            const int64_t rows = std::max(p->m, p->n);
+            const int64_t f = std::min<int64_t>(std::min(32, max_wgs), (rows + share_floor_rows() - 1) / share_floor_rows());
+            t = std::max(t, pow2_floor((int)std::max<int64_t>(1, f)));
+        }
         p->team = std::max(1, std::min(p->team, t));
     }
 }
@@ -588,7 +621,8 @@ static lra_status plan_launch(lra_ctx* ctx, std::vector<Prob*>& probs, int prec6
     for (Prob* p : probs) p->team = std::max(1, std::min(p->team, lp.max_wgs));
     share_teams(probs, lp.max_wgs);
     // every size class holds at least one team: halve the largest sizes until
-    // the classes fit the grid together
+    // the classes take at most half the grid together (the rest is shared out
+    // by work)
     for (;;) {
         std::vector<int> sizes;
         for (Prob* p : probs) sizes.push_back(p->team);
@@ -596,7 +630,7 @@ static lra_status plan_launch(lra_ctx* ctx, std::vector<Prob*>& probs, int prec6
         sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
         int64_t sum = 0;
         for (int s : sizes) sum += s;
-        if (sum <= lp.max_wgs) break;
+        if (sum <= std::max(1, lp.max_wgs / 2) || sizes.size() == 1) break;
         const int big = sizes.back();
         for (Prob* p : probs)
             if (p->team == big) p->team = std::max(1, big / 2);
@@ -1064,6 +1098,8 @@ struct Serve {
     int64_t tick_err_off = 0;       // state table and error words
     int tick_groups = 0;
     int64_t ticks = 0;
+    double tick_t0 = 0.0;           // host time of the in-flight tick's launch
+    size_t tick_active = 0;
 };
 
 static int64_t request_footprint(const Prob& p, int prec64)
@@ -1250,6 +1286,10 @@ static lra_status serve_launch(lra_ctx* ctx)
     HIP_TRY(hipMemcpyAsync(h + err_rb, dc + err_off, 8 * gs.size(), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipEventRecord(s.ev, ctx->stream));
     s.in_flight = true;
+    s.tick_t0 = now_us();
+    s.tick_active = s.active.size();
+    LRA_LOG(2, "tick %lld launched: %zu active (%zu admitted), %zu waiting, %zu launch(es)", (long long)s.ticks,
+            s.active.size(), admitted.size(), s.pending.size(), gs.size());
     s.tick_tbl_off = tbl_off;
     s.tick_err_off = err_rb;
     s.tick_groups = (int)gs.size();
@@ -1297,6 +1337,8 @@ static lra_status serve_complete(lra_ctx* ctx)
         }
     }
     s.active = keep;
+    LRA_LOG(2, "tick done after %.3f ms: %zu of %zu finished", (now_us() - s.tick_t0) * 1e-3, fin.size(),
+            s.tick_active);
     if (fin.empty()) return LRA_OK;
     // read back [I | J | G | U] of every completed request
     Layout L;

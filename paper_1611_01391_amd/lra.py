@@ -357,11 +357,13 @@ class Context:
 
     # -- batched ----------------------------------------------------------
     def ca_cur_batched(self, blocks: Sequence[tuple], raise_on_error: bool = True, **opts):
-        """blocks: sequence of (DeviceSource, k, sweeps, tol)."""
+        """blocks: sequence of (DeviceSource, k, sweeps, tol).  Returns
+        (worst status, list of Result); the index and nucleus arrays of all
+        blocks are views into shared buffers."""
         o = default_options(**opts)
         nb = len(blocks)
         arr = (Block * max(1, nb))()
-        bufs = []
+        kcaps = np.empty(max(1, nb), dtype=np.int64)
         for b, (src, k, sweeps, tol) in enumerate(blocks):
             arr[b].src = src.struct
             arr[b].m = src.m
@@ -369,17 +371,34 @@ class Context:
             arr[b].k = int(k)
             arr[b].sweeps = int(sweeps)
             arr[b].tol = float(tol)
-            bufs.append(_ResultBuf(max(int(k), o.k_max)))
+            kcaps[b] = max(int(k), o.k_max)
+        off = np.zeros(max(1, nb) + 1, dtype=np.int64)
+        off2 = np.zeros(max(1, nb) + 1, dtype=np.int64)
+        np.cumsum(kcaps[:nb], out=off[1:nb + 1])
+        np.cumsum(kcaps[:nb] * kcaps[:nb], out=off2[1:nb + 1])
+        I = np.zeros(max(1, off[nb]), dtype=np.int64)
+        J = np.zeros(max(1, off[nb]), dtype=np.int64)
+        G = np.zeros(max(1, off2[nb]))
+        U = np.zeros(max(1, off2[nb]))
         res_arr = (ResultC * max(1, nb))()
         for b in range(nb):
-            res_arr[b] = bufs[b].c
+            r = res_arr[b]
+            r.I = I.ctypes.data + 8 * int(off[b])
+            r.J = J.ctypes.data + 8 * int(off[b])
+            r.G = G.ctypes.data + 8 * int(off2[b])
+            r.U = U.ctypes.data + 8 * int(off2[b])
         st = lib().lra_ca_cur_batched(self._h, arr, nb, C.byref(o), res_arr)
         if st < 0 and raise_on_error and st not in (ERANK, ENONFINITE):
             raise LraError(st, "lra_ca_cur_batched")
         out = []
         for b in range(nb):
-            bufs[b].c = res_arr[b]
-            out.append(bufs[b].to_result())
+            r = res_arr[b]
+            k = max(0, r.k)
+            i0, g0 = int(off[b]), int(off2[b])
+            out.append(Result(r.status, k, I[i0:i0 + k], J[i0:i0 + k],
+                              G[g0:g0 + k * k].reshape(k, k), U[g0:g0 + k * k].reshape(k, k),
+                              r.sweeps_done, r.swaps_total, r.entries_read, r.err_est_rel,
+                              r.err_est_abs, r.err_mean, r.err_var, r.nucleus_cond1))
         return st, out
 
     # -- serving ----------------------------------------------------------

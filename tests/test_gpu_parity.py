@@ -272,3 +272,31 @@ def test_dependent_columns(ctx, prec):
         assert res.status == ref.status == lra.NUMERICAL_RANK and res.k == ref.k == kk
         np.testing.assert_array_equal(res.J, ref.J)
         np.testing.assert_array_equal(res.I, ref.I)
+
+
+def test_global_strip_path_matches_lds_path(ctx):
+    """Slices that do not fit LDS live in a global strip: capping the LDS for
+    strip rows (LRA_LDS_B_BYTES) forces that path; results are bit-identical."""
+    lra = _lra()
+    _say("global strip path")
+    A, d = synth.rect_factor_gaussian(7, 3000, 2200, 16, 1e-6, 16, n_cand=32)
+    At = torch.from_numpy(A).cuda()
+    kw = dict(init_cols=d.cand_cols, sample_rows=d.sample_rows, sample_cols=d.sample_cols)
+    ref = ctx.ca_cur(lra.dense(At), 16, 3, 0.0, **kw)
+    old = os.environ.get("LRA_LDS_B_BYTES")
+    os.environ["LRA_LDS_B_BYTES"] = "1024"
+    try:
+        c2 = lra.Context()
+    finally:
+        if old is None:
+            del os.environ["LRA_LDS_B_BYTES"]
+        else:
+            os.environ["LRA_LDS_B_BYTES"] = old
+    for team in (1, 4):
+        r = c2.ca_cur(lra.dense(At), 16, 3, 0.0, team_wgs=team, **kw)
+        assert r.status == ref.status and r.k == ref.k
+        np.testing.assert_array_equal(r.I, ref.I)
+        np.testing.assert_array_equal(r.J, ref.J)
+        np.testing.assert_array_equal(r.U, ref.U)
+        assert r.err_est_rel == ref.err_est_rel
+    c2.close()
