@@ -605,6 +605,8 @@ DI void basis_product(const Rows<T>& rw, int kd, const T* W, int wsd, int wsc)
     constexpr int CT = (KMAX + 15) / 16;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ntiles = (rw.nrows + 15) / 16;
+    // only the 4-deep steps and 16-wide column tiles that k reaches
+    const int kbn = (kd + 3) / 4, ctn = (kd + 15) / 16;
     for (int tile = wv; tile < ntiles; tile += NWAVE) {
         const int r = tile * 16 + (lane & 15);
         const bool rok = r < rw.nrows;
@@ -612,28 +614,34 @@ DI void basis_product(const Rows<T>& rw, int kd, const T* W, int wsd, int wsc)
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
             const int d = kb * 4 + (lane >> 4);
-            a[kb] = (rok && d < kd) ? rw.B[d * rw.ld + r] : (T)0;
+            a[kb] = (kb < kbn && rok && d < kd) ? rw.B[d * rw.ld + r] : (T)0;
         }
         acc_t out[CT];
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
             acc_t acc = {0, 0, 0, 0};
-            const int c = ct * 16 + (lane & 15);
+            if (ct < ctn) {
+                const int c = ct * 16 + (lane & 15);
 #pragma unroll
-            for (int kb = 0; kb < KB; ++kb) {
-                const int d = kb * 4 + (lane >> 4);
-                const T w = (d < kd && c < kd) ? W[d * wsd + c * wsc] : (T)0;
-                acc = mfma16(a[kb], w, acc);
+                for (int kb = 0; kb < KB; ++kb) {
+                    if (kb < kbn) {
+                        const int d = kb * 4 + (lane >> 4);
+                        const T w = (d < kd && c < kd) ? W[d * wsd + c * wsc] : (T)0;
+                        acc = mfma16(a[kb], w, acc);
+                    }
+                }
             }
             out[ct] = acc;
         }
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
-            const int c = ct * 16 + (lane & 15);
+            if (ct < ctn) {
+                const int c = ct * 16 + (lane & 15);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int rr = tile * 16 + Acc4<T>::row(lane, e);
-                if (rr < rw.nrows && c < kd) rw.B[c * rw.ld + rr] = out[ct][e];
+                for (int e = 0; e < 4; ++e) {
+                    const int rr = tile * 16 + Acc4<T>::row(lane, e);
+                    if (rr < rw.nrows && c < kd) rw.B[c * rw.ld + rr] = out[ct][e];
+                }
             }
         }
     }
