@@ -162,6 +162,12 @@ def bench_dense(args, plain=False):
     src = lra.dense(At)
     kw = dict(init_cols=d.cand_cols, sample_rows=d.sample_rows, sample_cols=d.sample_cols,
               precision=prec, team_wgs=args.team)
+    tuned = None
+    if args.autotune and not args.team:
+        team, tms = ctx.autotune_team(src, k, sweeps, 0.0, init_cols=d.cand_cols, sample_rows=d.sample_rows,
+                                      sample_cols=d.sample_cols, precision=prec)
+        tuned = {"team_wgs": team, "kernel_ms": tms}
+        log(f"# autotuned team: {team} workgroups ({tms:.3f} ms)")
     el, st, res = _timed_steps(ctx, torch, lambda: ctx.ca_cur(src, k, sweeps, 0.0, **kw), args.steps, args.warmup)
     ms_per_step = el * 1e3 / args.steps
     kernel_ms = st["engine_ms_total"] / max(1, st["launches"])
@@ -189,7 +195,7 @@ def bench_dense(args, plain=False):
     out = _base(args, args.steps / el, "CUR LRAs/s", ms_per_step,
                 "f64" if prec == lra.PREC_FP64 else "f32",
                 {"workload": desc, "m": n, "n": n, "k": k, "sweeps": sweeps,
-                 "precision": "fp64" if prec == lra.PREC_FP64 else "mixed"})
+                 "precision": "fp64" if prec == lra.PREC_FP64 else "mixed", "autotuned": tuned})
     traffic = None
     if not plain and (n, k, sweeps, args.precision) == (16384, 32, 4, "fp64"):
         traffic = _profiled_traffic("engine_kernel_dense16384_k32.md")
@@ -282,6 +288,11 @@ def bench_multipole(args):
     prec = lra.PREC_FP64 if f64 else lra.PREC_MIXED
     jobs = [(lra.invdist(xd[a0:a1], xd[b0:b1]), 8, 4, tol) for (a0, a1, b0, b1) in blocks]
     ctx = lra.Context()
+    tuned = None
+    if args.autotune:
+        floor, fms = ctx.autotune_batched(jobs, k_max=kmax, precision=prec, seed=args.seed)
+        tuned = {"floor_rows": floor, "kernel_ms": fms}
+        log(f"# autotuned planning floor: {floor} rows ({fms:.2f} ms)")
     el, st, (bst, out_b) = _timed_steps(
         ctx, torch, lambda: ctx.ca_cur_batched(jobs, raise_on_error=False, k_max=kmax, precision=prec,
                                                seed=args.seed),
@@ -338,7 +349,8 @@ def bench_multipole(args):
                 {"workload": f"1D multipole far field: N = {N} mixture points, adaptive binary tree (leaves <= 4096), "
                              f"{len(blocks)} admissible blocks (dist >= width, min side 96), kernel 1/|x-y|, "
                              f"adaptive k 8..{kmax} step 8 to tol {tol:g}, one batched launch",
-                 "points": N, "blocks": len(blocks), "tol": tol, "k_max": kmax, "precision": args.precision})
+                 "points": N, "blocks": len(blocks), "tol": tol, "k_max": kmax, "precision": args.precision,
+                 "autotuned": tuned})
     out["roofline"] = _alu_roofline(entries, kernel_ms)
     out["cpu_baseline"] = cpu
     out["batched_vs_plain"] = {"batched_blocks_per_s": len(blocks) / batched_s,
@@ -539,6 +551,8 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--team", type=int, default=0)
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="skip the team / planning-floor search before the timed steps")
     args = ap.parse_args()
 
     if args.gpus != 1:

@@ -222,6 +222,29 @@ lra_status lra_wait(lra_ctx* ctx, uint64_t ticket);
  * Errors: LRA_EINVAL. */
 lra_status lra_serve_config(lra_ctx* ctx, size_t arena_bytes, int phases_per_tick, int max_active);
 
+/* Autotuning (a search of this library, not a step of the method): each
+ * call times its candidates on the context's stream (HIP events around the
+ * engine launches, one warm-up, median of the rest), keeps the fastest in
+ * the context for later calls, and returns it.
+ *
+ * lra_autotune_team: workgroups per problem for single problems of this
+ *   size class (precision, rank bucket, bit length of max(m, n)); the
+ *   candidates are the automatic choice a and a/4, a/2, 3a/2, 2a, 4a within
+ *   the co-resident grid.  Results of the timed runs are discarded.
+ * lra_autotune_batched: the planning floor of shared launches (batched calls
+ *   and serving ticks: a problem keeps at least ceil(rows / floor) workgroups,
+ *   at most 32; 0 = none), over 0, 2048, ..., 65536 rows, on a
+ *   representative batch.
+ * lra_tuning_save / lra_tuning_load: the context's tuned values as a text
+ *   file ("team <class> <workgroups>", "floor <rows>").
+ * Errors: LRA_EINVAL, and those of lra_ca_cur / lra_ca_cur_batched. */
+lra_status lra_autotune_team(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k, int sweeps,
+                             double tol, const lra_options* opts, int* best_team, double* best_ms);
+lra_status lra_autotune_batched(lra_ctx* ctx, const lra_block* blocks, int nblocks, const lra_options* opts,
+                                int64_t* best_floor_rows, double* best_ms);
+lra_status lra_tuning_save(lra_ctx* ctx, const char* path);
+lra_status lra_tuning_load(lra_ctx* ctx, const char* path);
+
 /* Kernel timing of a context.  With timing enabled, HIP events on the
  * context's stream bracket every engine launch; engine_ms_total accumulates
  * their elapsed times and last_engine_ms holds the latest one. */

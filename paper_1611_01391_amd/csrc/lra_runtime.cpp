@@ -128,7 +128,8 @@ struct lra_ctx {
     Buffer dev;              // workspace for blocking calls
     Buffer host;             // pinned staging for blocking calls
     int64_t dev_in_use = 0;  // bytes held by the serving slots
-    std::map<std::string, int> tuned;  // autotuned team sizes
+    std::map<std::string, int> tuned;  // autotuned team sizes by size class
+    int64_t floor_rows = -1;           // autotuned planning floor (-1: default)
     bool timing = false;
     bool trace = false;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -354,17 +355,27 @@ static int strip_lds(lra_ctx* ctx, int prec64, int kmx)
     return b;
 }
 
-// Workgroups per problem: enough that each workgroup's rows fit its LDS,
-// within the co-resident limit; an explicit or tuned choice overrides.
-static int auto_team(lra_ctx* ctx, const Prob& p, int prec64)
+// Size class of a single problem for the tuned team sizes: precision, rank
+// bucket and the bit length of its longer side.
+static std::string team_key(const Prob& p, int prec64)
 {
-    const int esz = prec64 ? 8 : 4;
     const int64_t M = std::max(p.m, p.n);
     char key[96];
     std::snprintf(key, sizeof(key), "%d/%d/%lld", prec64, kmax_bucket(p.kcap),
                   (long long)(64 - __builtin_clzll((unsigned long long)M)));
-    auto it = ctx->tuned.find(key);
-    if (it != ctx->tuned.end()) return it->second;
+    return key;
+}
+
+// Workgroups per problem: enough that each workgroup's rows fit its LDS,
+// within the co-resident limit; an explicit or tuned choice overrides.
+static int auto_team(lra_ctx* ctx, const Prob& p, int prec64, bool use_tuned = true)
+{
+    const int esz = prec64 ? 8 : 4;
+    const int64_t M = std::max(p.m, p.n);
+    if (use_tuned) {
+        auto it = ctx->tuned.find(team_key(p, prec64));
+        if (it != ctx->tuned.end()) return it->second;
+    }
     int64_t rows_fit = strip_lds(ctx, prec64, kmax_bucket(p.kcap)) / ((int64_t)p.kcap * esz);
     // at most one row per thread keeps the swap loop register-resident
     rows_fit = std::max<int64_t>(64, std::min<int64_t>(rows_fit, NT));
@@ -582,7 +593,7 @@ static int pow2_floor(int v)
 // problem's share of the grid's workgroups (a power of two, at least one),
 // never more than the latency-optimal size the problem came with, so that
 // large and small problems finish together.
-static void share_teams(std::vector<Prob*>& probs, int max_wgs)
+static void share_teams(std::vector<Prob*>& probs, int max_wgs, int64_t floor_rows)
 {
     if (probs.size() < 2) return;
     double tot = 0.0;
@@ -591,9 +602,9 @@ static void share_teams(std::vector<Prob*>& probs, int max_wgs)
         if (p->team_fixed) continue;
         const double share = (double)max_wgs * prob_cost(*p) / std::max(tot, 1.0);
         int t = pow2_floor((int)std::max(1.0, std::min(share, (double)max_wgs)));
-        if (share_floor_rows() > 0) {
+        if (floor_rows > 0) {
             const int64_t rows = std::max(p->m, p->n);
-            const int64_t f = std::min<int64_t>(std::min(32, max_wgs), (rows + share_floor_rows() - 1) / share_floor_rows());
+            const int64_t f = std::min<int64_t>(std::min(32, max_wgs), (rows + floor_rows - 1) / floor_rows);
             t = std::max(t, pow2_floor((int)std::max<int64_t>(1, f)));
         }
         p->team = std::max(1, std::min(p->team, t));
@@ -619,7 +630,7 @@ static lra_status plan_launch(lra_ctx* ctx, std::vector<Prob*>& probs, int prec6
     if (occ < 1) return LRA_EDEVICE;
     lp.max_wgs = occ * ctx->num_cu;
     for (Prob* p : probs) p->team = std::max(1, std::min(p->team, lp.max_wgs));
-    share_teams(probs, lp.max_wgs);
+    share_teams(probs, lp.max_wgs, ctx->floor_rows >= 0 ? ctx->floor_rows : share_floor_rows());
     // every size class holds at least one team: halve the largest sizes until
     // the classes take at most half the grid together (the rest is shared out
     // by work)
@@ -1480,6 +1491,156 @@ extern "C" lra_status lra_wait(lra_ctx* ctx, uint64_t ticket)
         }
         if (!had_work) return LRA_EDEVICE;  // nothing could advance the ticket
     }
+}
+
+
+// ----------------------------------------------------------------------------
+// autotuning: time candidates with HIP events, keep the fastest in the context
+// ----------------------------------------------------------------------------
+
+// Median engine time of `reps` runs (after one warm-up) of a problem set.
+static lra_status time_batch(lra_ctx* ctx, std::vector<Prob> probs, int prec64, int reps, double* ms)
+{
+    std::vector<lra_result> res(probs.size());
+    std::vector<lra_result*> rp(probs.size());
+    for (size_t i = 0; i < probs.size(); ++i) {
+        std::memset(&res[i], 0, sizeof(lra_result));
+        rp[i] = &res[i];
+    }
+    const bool was_timing = ctx->timing;
+    const lra_stats saved = ctx->stats;
+    if (!ctx->ev0) {
+        HIP_TRY(hipEventCreate(&ctx->ev0));
+        HIP_TRY(hipEventCreate(&ctx->ev1));
+    }
+    ctx->timing = true;
+    std::vector<double> t;
+    lra_status rs = LRA_OK;
+    for (int r = 0; r <= reps && rs == LRA_OK; ++r) {
+        std::vector<Prob> copy = probs;
+        rs = run_batch(ctx, copy, prec64, 1 << 30, rp.data());
+        if (r > 0) t.push_back(ctx->stats.last_engine_ms);
+    }
+    ctx->timing = was_timing;
+    ctx->stats = saved;
+    if (rs != LRA_OK) return rs;
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    return LRA_OK;
+}
+
+extern "C" lra_status lra_autotune_team(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k, int sweeps,
+                                        double tol, const lra_options* opts, int* best_team, double* best_ms)
+{
+    if (!ctx) return LRA_EINVAL;
+    lra_options o;
+    if (opts) o = *opts;
+    else lra_default_options(&o);
+    std::vector<Prob> probs(1);
+    lra_status rs = make_prob(src, m, n, k, sweeps, tol, &o, probs[0], 0);
+    if (rs != LRA_OK) return rs;
+    const int prec64 = o.precision == LRA_PREC_FP64;
+    const int base = auto_team(ctx, probs[0], prec64, false);
+    int occ = 0;
+    const int kmx = kmax_bucket(probs[0].kcap);
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, engine_kernel_ptr(prec64, kmx), NT,
+                                                         engine_smem_fixed(prec64, kmx) + strip_lds(ctx, prec64, kmx)));
+    const int cap = std::min(NT, std::max(1, occ) * ctx->num_cu);
+    std::vector<int> cand = {std::max(1, base / 4), std::max(1, base / 2), base, std::min(cap, base + base / 2),
+                             std::min(cap, base * 2), std::min(cap, base * 4)};
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    int best = base;
+    double bms = 1e300;
+    for (int c : cand) {
+        probs[0].team = c;
+        probs[0].team_fixed = true;
+        double ms = 0.0;
+        rs = time_batch(ctx, probs, prec64, 3, &ms);
+        if (rs != LRA_OK) return rs;
+        LRA_LOG(1, "autotune team %d: %.3f ms", c, ms);
+        if (ms < bms) {
+            bms = ms;
+            best = c;
+        }
+    }
+    ctx->tuned[team_key(probs[0], prec64)] = best;
+    if (best_team) *best_team = best;
+    if (best_ms) *best_ms = bms;
+    return LRA_OK;
+}
+
+extern "C" lra_status lra_autotune_batched(lra_ctx* ctx, const lra_block* blocks, int nblocks, const lra_options* opts,
+                                           int64_t* best_floor_rows, double* best_ms)
+{
+    if (!ctx || nblocks < 1 || !blocks) return LRA_EINVAL;
+    lra_options o;
+    if (opts) o = *opts;
+    else lra_default_options(&o);
+    if (o.init_cols || o.sample_rows || o.sample_cols) return LRA_EINVAL;
+    const int prec64 = o.precision == LRA_PREC_FP64;
+    std::vector<Prob> probs(nblocks);
+    for (int b = 0; b < nblocks; ++b) {
+        const lra_block& bl = blocks[b];
+        lra_status rs = make_prob(&bl.src, bl.m, bl.n, bl.k, bl.sweeps, bl.tol, &o, probs[b], b);
+        if (rs != LRA_OK) return rs;
+        probs[b].team = o.team_wgs > 0 ? std::min(o.team_wgs, NT)
+                                       : std::min(NT, pow2_ceil(auto_team(ctx, probs[b], prec64)));
+        probs[b].team_fixed = o.team_wgs > 0;
+    }
+    const int64_t saved = ctx->floor_rows;
+    int64_t best = share_floor_rows();
+    double bms = 1e300;
+    for (int64_t f : {(int64_t)0, (int64_t)2048, (int64_t)4096, (int64_t)8192, (int64_t)16384, (int64_t)32768,
+                      (int64_t)65536}) {
+        ctx->floor_rows = f;
+        double ms = 0.0;
+        lra_status rs = time_batch(ctx, probs, prec64, 2, &ms);
+        if (rs != LRA_OK) {
+            ctx->floor_rows = saved;
+            return rs;
+        }
+        LRA_LOG(1, "autotune floor %lld rows: %.3f ms", (long long)f, ms);
+        if (ms < bms) {
+            bms = ms;
+            best = f;
+        }
+    }
+    ctx->floor_rows = best;
+    if (best_floor_rows) *best_floor_rows = best;
+    if (best_ms) *best_ms = bms;
+    return LRA_OK;
+}
+
+extern "C" lra_status lra_tuning_save(lra_ctx* ctx, const char* path)
+{
+    if (!ctx || !path) return LRA_EINVAL;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return LRA_EINVAL;
+    std::fprintf(f, "# lra tuning: team <precision/rank bucket/size bits> <workgroups>; floor <rows>\n");
+    for (auto& kv : ctx->tuned) std::fprintf(f, "team %s %d\n", kv.first.c_str(), kv.second);
+    if (ctx->floor_rows >= 0) std::fprintf(f, "floor %lld\n", (long long)ctx->floor_rows);
+    std::fclose(f);
+    return LRA_OK;
+}
+
+extern "C" lra_status lra_tuning_load(lra_ctx* ctx, const char* path)
+{
+    if (!ctx || !path) return LRA_EINVAL;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return LRA_EINVAL;
+    char line[256];
+    lra_status rs = LRA_OK;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        char kind[16], key[96];
+        long long v = 0;
+        if (std::sscanf(line, "team %95s %lld", key, &v) == 2 && v >= 1 && v <= NT) ctx->tuned[key] = (int)v;
+        else if (std::sscanf(line, "floor %lld", &v) == 1 && v >= 0) ctx->floor_rows = v;
+        else if (std::sscanf(line, "%15s", kind) == 1) rs = LRA_EINVAL;
+    }
+    std::fclose(f);
+    return rs;
 }
 
 extern "C" lra_status lra_set_timing(lra_ctx* ctx, int enable, int reset)

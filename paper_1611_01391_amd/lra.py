@@ -27,6 +27,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 # every entry point declared in include/lra.h
 EXPORTS = ["lra_default_options", "lra_create", "lra_destroy", "lra_ca_cur", "lra_maxvol",
            "lra_ca_cur_batched", "lra_submit", "lra_poll", "lra_wait", "lra_serve_config", "lra_set_timing",
+           "lra_autotune_team", "lra_autotune_batched", "lra_tuning_save", "lra_tuning_load",
            "lra_get_stats", "lra_status_str", "lra_version"]
 
 
@@ -112,6 +113,17 @@ def lib():
         L.lra_wait.restype = C.c_int
         L.lra_serve_config.argtypes = [P, C.c_size_t, C.c_int, C.c_int]
         L.lra_serve_config.restype = C.c_int
+        L.lra_autotune_team.argtypes = [P, C.POINTER(Source), C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                        C.c_double, C.POINTER(Options), C.POINTER(C.c_int),
+                                        C.POINTER(C.c_double)]
+        L.lra_autotune_team.restype = C.c_int
+        L.lra_autotune_batched.argtypes = [P, C.POINTER(Block), C.c_int, C.POINTER(Options),
+                                           C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.lra_autotune_batched.restype = C.c_int
+        L.lra_tuning_save.argtypes = [P, C.c_char_p]
+        L.lra_tuning_save.restype = C.c_int
+        L.lra_tuning_load.argtypes = [P, C.c_char_p]
+        L.lra_tuning_load.restype = C.c_int
         L.lra_set_timing.argtypes = [P, C.c_int, C.c_int]
         L.lra_set_timing.restype = C.c_int
         L.lra_get_stats.argtypes = [P, C.POINTER(Stats)]
@@ -354,6 +366,58 @@ class Context:
         if st < 0:
             raise LraError(st, "lra_maxvol")
         return dict(I=I[:ke.value].copy(), swaps=sw.value, k_eff=ke.value, status=st)
+
+    # -- autotuning -------------------------------------------------------
+    def autotune_team(self, src: DeviceSource, k: int, sweeps: int, tol: float = 0.0, *,
+                      init_cols=None, sample_rows=None, sample_cols=None, **opts):
+        """Time team sizes for problems of this size class; returns (team, ms)."""
+        o = default_options(**opts)
+        cand, Q, S = _i64(init_cols), _i64(sample_rows), _i64(sample_cols)
+        if cand is not None:
+            o.init_cols = cand.ctypes.data
+            o.n_init_cols = len(cand)
+        if Q is not None:
+            o.sample_rows = Q.ctypes.data
+            o.sample_q = len(Q)
+        if S is not None:
+            o.sample_cols = S.ctypes.data
+            o.sample_s = len(S)
+        team = C.c_int(0)
+        ms = C.c_double(0.0)
+        st = lib().lra_autotune_team(self._h, C.byref(src.struct), src.m, src.n, int(k), int(sweeps),
+                                     float(tol), C.byref(o), C.byref(team), C.byref(ms))
+        if st != OK:
+            raise LraError(st, "lra_autotune_team")
+        return team.value, ms.value
+
+    def autotune_batched(self, blocks: Sequence[tuple], **opts):
+        """Time planning floors for shared launches; returns (floor_rows, ms)."""
+        o = default_options(**opts)
+        nb = len(blocks)
+        arr = (Block * max(1, nb))()
+        for b, (src, k, sweeps, tol) in enumerate(blocks):
+            arr[b].src = src.struct
+            arr[b].m = src.m
+            arr[b].n = src.n
+            arr[b].k = int(k)
+            arr[b].sweeps = int(sweeps)
+            arr[b].tol = float(tol)
+        fl = C.c_int64(0)
+        ms = C.c_double(0.0)
+        st = lib().lra_autotune_batched(self._h, arr, nb, C.byref(o), C.byref(fl), C.byref(ms))
+        if st != OK:
+            raise LraError(st, "lra_autotune_batched")
+        return fl.value, ms.value
+
+    def tuning_save(self, path: str):
+        st = lib().lra_tuning_save(self._h, path.encode())
+        if st != OK:
+            raise LraError(st, "lra_tuning_save")
+
+    def tuning_load(self, path: str):
+        st = lib().lra_tuning_load(self._h, path.encode())
+        if st != OK:
+            raise LraError(st, "lra_tuning_load")
 
     # -- batched ----------------------------------------------------------
     def ca_cur_batched(self, blocks: Sequence[tuple], raise_on_error: bool = True, **opts):

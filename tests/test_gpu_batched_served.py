@@ -313,3 +313,40 @@ def test_cauchy_full_size(ctx, prec):
     _vs_oracle(res, ref, f"cauchy {prec}", oracle.cauchy(s.astype(np.float64), t.astype(np.float64)),
                d.sample_rows, d.sample_cols, tol=tol, gamma=GAMMA64 if prec == "f64" else 1e-3)
     assert res.status >= 0 and res.err_est_rel <= tol
+
+
+# ---------------------------------------------------------------------------
+# autotuning
+# ---------------------------------------------------------------------------
+
+def test_autotune_keeps_results_and_round_trips(ctx, tmp_path):
+    lra = _lra()
+    _say("autotune")
+    c = lra.Context()
+    A, d = synth.plain_fp64(4)
+    src = lra.dense(torch.from_numpy(A).cuda())
+    kw = dict(init_cols=d.cand_cols, sample_rows=d.sample_rows, sample_cols=d.sample_cols)
+    before = ctx.ca_cur(src, 8, 3, 0.0, **kw)
+    team, ms = c.autotune_team(src, 8, 3, 0.0, **kw)
+    assert 1 <= team <= 256 and ms > 0
+    after = c.ca_cur(src, 8, 3, 0.0, **kw)
+    _same(after, before, "tuned team")
+    x, blocks = _multipole_case(1 << 14, 256)
+    xd = torch.from_numpy(x).cuda()
+    jobs = [(lra.invdist(xd[a0:a1], xd[b0:b1]), 8, 4, 1e-8) for (a0, a1, b0, b1) in blocks]
+    _, ref = ctx.ca_cur_batched(jobs, raise_on_error=False, k_max=48)
+    floor, ms = c.autotune_batched(jobs, k_max=48)
+    assert floor in (0, 2048, 4096, 8192, 16384, 32768, 65536) and ms > 0
+    _, out = c.ca_cur_batched(jobs, raise_on_error=False, k_max=48)
+    for b in range(0, len(blocks), 9):
+        _same(out[b], ref[b], f"tuned block {b}")
+    path = str(tmp_path / "tuning.txt")
+    c.tuning_save(path)
+    text = open(path).read()
+    assert f"floor {floor}" in text and f" {team}\n" in text
+    c2 = lra.Context()
+    c2.tuning_load(path)
+    c2.tuning_save(str(tmp_path / "again.txt"))
+    assert open(str(tmp_path / "again.txt")).read() == text
+    c.close()
+    c2.close()
