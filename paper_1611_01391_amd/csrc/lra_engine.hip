@@ -159,8 +159,8 @@ template <typename T, int KMAX>
 struct Smem {
     int64_t I[KMAX], J[KMAX], prevI[KMAX], prevJ[KMAX];
     double AUG[KMAX * 2 * KMAX];  // [M | right-hand sides], row stride 2 KMAX (T view for the strip)
-    double fcol[KMAX];            // multipliers / column of U of the current step
-    double diag[KMAX];            // pivots of the current factorisation
+    double lucol[KMAX];           // register LU: the pivot column, one entry per lane
+    double lumul[KMAX];           // register LU: the multipliers of the current step
     double red[NT];           // fixed-order reductions
     double pts[KMAX];         // coordinates of the fixed index set (generated sources)
     T g[KMAX];                // swap update vector
@@ -413,10 +413,9 @@ DI float readlane_t(float v, int lane)
 // the multiplier of row s reaches every lane by a lane read.  Lanes without
 // a column of their own address column t instead, which is dead by then
 // (its rows past the pivot are never read again), so the loads and stores
-// need no per-lane branches and stay pipelined.  lu_aug_solve is called by
-// the whole workgroup (barriers on entry and exit), lu_aug_wave0 by
-// wavefront 0 alone.  Writes sm.ok (0 on an exact zero pivot) and sm.minpiv
-// (the smallest pivot modulus).
+// need no per-lane branches and stay pipelined.  Wavefront 0 alone; writes
+// sm.ok (0 on an exact zero pivot) and sm.minpiv (the smallest pivot
+// modulus).
 template <typename T, int KMAX, typename LT, int LD, int NB>
 DI void lu_aug_wave0(LT* A, int k, int rhs0, int nr, Smem<T, KMAX>& sm)
 {
@@ -562,12 +561,219 @@ DI void unit_lower_inv_wave0(T* A, int k)
     }
 }
 
-template <typename T, int KMAX, typename LT, int LD, int NB>
-DI void lu_aug_solve(LT* A, int k, int rhs0, int nr, Smem<T, KMAX>& sm)
+
+// A column of up to KR values of type LT held in registers, readable and
+// writable at a wavefront-uniform run-time row (lowered to register-indexed
+// moves; a vector of at most 32 dwords stays in registers, larger arrays
+// would go to scratch).  binary64: 16 rows per vector, as dword pairs.
+typedef uint32_t u32x32 __attribute__((ext_vector_type(32)));
+
+template <typename LT, int KR>
+struct RegCol;
+
+template <int KR>
+struct RegCol<double, KR> {
+    static constexpr int NV = (KR + 15) / 16;
+    u32x32 v[NV];
+    DI double get(int r) const
+    {
+        const u32x32& w = v[r >> 4];
+        const int e = 2 * (r & 15);
+        return __longlong_as_double((long long)(((uint64_t)w[e + 1] << 32) | w[e]));
+    }
+    DI void set(int r, double x)
+    {
+        u32x32& w = v[r >> 4];
+        const int e = 2 * (r & 15);
+        const uint64_t b = (uint64_t)__double_as_longlong(x);
+        w[e] = (uint32_t)b;
+        w[e + 1] = (uint32_t)(b >> 32);
+    }
+    // i uniform across the wavefront; every chunk is indexed (no branch,
+    // so no copies of whole vectors), the owning chunk's value is kept
+    DI double dget(int i) const
+    {
+        double x = get_in(v[0], i & 15);
+#pragma unroll
+        for (int c = 1; c < NV; ++c) {
+            const double y = get_in(v[c], i & 15);
+            x = (i >> 4) == c ? y : x;
+        }
+        return x;
+    }
+    DI void dset(int i, double x)
+    {
+#pragma unroll
+        for (int c = 0; c < NV; ++c) {
+            const double old = get_in(v[c], i & 15);
+            set_in(v[c], i & 15, (i >> 4) == c ? x : old);
+        }
+    }
+    static DI double get_in(const u32x32& w, int j)
+    {
+        return __longlong_as_double((long long)(((uint64_t)w[2 * j + 1] << 32) | w[2 * j]));
+    }
+    static DI void set_in(u32x32& w, int j, double x)
+    {
+        const uint64_t b = (uint64_t)__double_as_longlong(x);
+        w[2 * j] = (uint32_t)b;
+        w[2 * j + 1] = (uint32_t)(b >> 32);
+    }
+};
+
+template <int KR>
+struct RegCol<float, KR> {
+    static_assert(KR <= 32, "one vector");
+    u32x32 v;
+    DI float get(int r) const { return __uint_as_float(v[r]); }
+    DI void set(int r, float x) { v[r] = __float_as_uint(x); }
+    DI float dget(int i) const { return __uint_as_float(v[i]); }
+    DI void dset(int i, float x) { v[i] = __float_as_uint(x); }
+};
+
+// The same solve with the matrix in registers, for k <= KR <= 32: lane c
+// holds column c (and c + 64 when NB = 2) of [M | R], rows 0..KR-1, loaded
+// once from A and the right-hand-side block stored back at the end, so the
+// elimination makes no LDS or global round trip per row.  Per step, lane t
+// passes its column through sm.lucol for the pivot search (lane s = row s)
+// and sm.lumul carries the multipliers back.  Rows are not interchanged:
+// lane s tracks the position its row would have after the interchanges
+// (pos), which breaks ties exactly as the interchanging form does, and every
+// row sees the same operations in the same order, so the results are the
+// same bits.  pv (lane t) is the row chosen at step t; one pass puts the rows
+// in pivot order before the back substitution.
+template <typename T, int KMAX, typename LT, int LD, int KR, int NB>
+DI void lu_reg_wave0(LT* A, int k, int rhs0, int nr, Smem<T, KMAX>& sm)
 {
-    __syncthreads();
-    if (threadIdx.x < 64) lu_aug_wave0<T, KMAX, LT, LD, NB>(A, k, rhs0, nr, sm);
-    __syncthreads();
+    static_assert(KR <= KMAX && KR <= 32, "rows in registers");
+    const int lane = threadIdx.x;
+    const int W = k + nr;
+    int lc[NB];
+    bool act[NB];
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb) {
+        const int cc = lane + 64 * jb;
+        act[jb] = cc < W;
+        lc[jb] = cc < k ? cc : (act[jb] ? rhs0 + cc - k : 0);
+    }
+    RegCol<LT, KR> a[NB];
+#pragma unroll
+    for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int r = 0; r < KR; ++r) {
+            const LT v = A[(r < k ? r : 0) * LD + lc[jb]];
+            a[jb].set(r, (act[jb] && r < k) ? v : (LT)0);
+        }
+    LT* cb = (LT*)sm.lucol;
+    LT* lb = (LT*)sm.lumul;
+    double minpiv = INFINITY;
+    int ok = 1;
+    LT dreg = (LT)0;    // lane t: pivot of step t
+    int pv = 0;         // lane t: row chosen at step t
+    int pos = lane;     // lane s: position of row s
+    bool used = false;  // lane s: row s already a pivot row
+    for (int t = 0; t < k; ++t) {
+        if (lane == t) {
+#pragma unroll
+            for (int r = 0; r < KR; ++r) cb[r] = a[0].get(r);
+        }
+        wave_lds_sync();
+        const LT cv = cb[lane < KR ? lane : 0];  // lane s: entry s of column t
+        K2 key = (!used && lane < k) ? k2_make(fabs((double)cv), pos, lane) : k2_none();
+        key = wave_argmax(key);
+        const double pav = k2_val(key);
+        if (pav == 0.0) {
+            ok = 0;
+            break;
+        }
+        minpiv = fmin(minpiv, pav);
+        const int p = k2_col(key);
+        const LT piv = readlane_t(cv, p);
+        if (lane == t) {
+            dreg = piv;
+            pv = p;
+        }
+        const int ppos = __builtin_amdgcn_readlane(pos, p);
+        const LT lm = (!used && lane < k && lane != p) ? cv / piv : (LT)0;
+        if (lane < KR) lb[lane] = lm;
+        pos = lane == p ? t : (pos == t ? ppos : pos);
+        used = used || lane == p;
+        LT prow[NB];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) prow[jb] = a[jb].dget(p);
+        wave_lds_sync();
+        LT f[KR];
+#pragma unroll
+        for (int r = 0; r < KR; ++r) f[r] = lb[r];
+#pragma unroll
+        for (int rb = 0; rb < KR; rb += 4) {
+            if (rb < k) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb) a[jb].set(rb + i, a[jb].get(rb + i) - f[rb + i] * prow[jb]);
+            }
+        }
+        wave_lds_sync();
+    }
+    if (ok) {
+        // rows in pivot order
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+            RegCol<LT, KR> b;
+#pragma unroll
+            for (int t = 0; t < KR; ++t) b.set(t, t < k ? a[jb].dget(__builtin_amdgcn_readlane(pv, t)) : (LT)0);
+            a[jb] = b;
+        }
+        bool rhs[NB];
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) rhs[jb] = act[jb] && lane + 64 * jb >= k;
+#pragma unroll
+        for (int t = KR - 1; t >= 0; --t) {
+            if (t < k) {
+                const LT d = readlane_t(dreg, t);
+                LT x[NB];
+#pragma unroll
+                for (int jb = 0; jb < NB; ++jb) {
+                    x[jb] = rhs[jb] ? a[jb].get(t) / d : (LT)0;
+                    a[jb].set(t, rhs[jb] ? x[jb] : a[jb].get(t));
+                }
+#pragma unroll
+                for (int s2 = 0; s2 < t; ++s2) {
+                    const LT u = readlane_t(a[0].get(s2), t);
+#pragma unroll
+                    for (int jb = 0; jb < NB; ++jb) a[jb].set(s2, a[jb].get(s2) - u * x[jb]);
+                }
+            }
+        }
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+            if (rhs[jb])
+#pragma unroll
+                for (int r = 0; r < KR; ++r)
+                    if (r < k) A[r * LD + lc[jb]] = a[jb].get(r);
+        }
+    }
+    if (lane == 0) {
+        sm.ok = ok;
+        sm.minpiv = minpiv;
+    }
+}
+
+// The wavefront-0 solve: rows in registers up to k = 32 (NBR column blocks,
+// k + nr <= 64 NBR), else the LDS form.
+template <typename T, int KMAX, typename LT, int LD, int NB, int NBR>
+DI void lu_solve_wave0(LT* A, int k, int rhs0, int nr, Smem<T, KMAX>& sm)
+{
+    constexpr int K16 = KMAX < 16 ? KMAX : 16, K32 = KMAX < 32 ? KMAX : 32;
+    if (k <= 8)
+        lu_reg_wave0<T, KMAX, LT, LD, 8, NBR>(A, k, rhs0, nr, sm);
+    else if (k <= K16)
+        lu_reg_wave0<T, KMAX, LT, LD, K16, NBR>(A, k, rhs0, nr, sm);
+    else if (k <= K32)
+        lu_reg_wave0<T, KMAX, LT, LD, K32, NBR>(A, k, rhs0, nr, sm);
+    else
+        lu_aug_wave0<T, KMAX, LT, LD, NB>(A, k, rhs0, nr, sm);
 }
 
 // ----------------------------------------------------------------------------
@@ -759,7 +965,7 @@ NOINL double gather_phase(const TaskDesc& td, Team& tio, int transpose, int warm
     __syncthreads();
     double lmax = 0.0;
     if (warm) {
-        if (threadIdx.x < 64) lu_aug_wave0<T, KMAX, T, 2 * KMAX, (2 * KMAX + 63) / 64>((T*)sm.AUG, k, KMAX, k, sm);
+        if (threadIdx.x < 64) lu_solve_wave0<T, KMAX, T, 2 * KMAX, (2 * KMAX + 63) / 64, 1>((T*)sm.AUG, k, KMAX, k, sm);
         else lmax = gather_rows<T, KMAX>(td.src, transpose, sm, F, k, rw, threadIdx.x - 64, NT - 64);
     } else {
         lmax = gather_rows<T, KMAX>(td.src, transpose, sm, F, k, rw, threadIdx.x, NT);
@@ -1163,7 +1369,7 @@ DI void final_core(const TaskDesc& td, Team& tio)
     // U = G^{-1} and W = G^{-1} A[I,S] by one partial-pivot LU solve on
     // wavefront 0, while the other wavefronts fetch A[Q,J] and A[Q,S]
     if (threadIdx.x < 64) {
-        lu_aug_wave0<T, KMAX, double, LDF, (2 * KMAX + 127) / 64>(Fm, k, KMAX, k + s, sm);
+        lu_solve_wave0<T, KMAX, double, LDF, (2 * KMAX + 127) / 64, 2>(Fm, k, KMAX, k + s, sm);
     } else {
         for (int e = threadIdx.x - 64; e < q * k; e += NT - 64) AQJ[e] = entry64(td.src, td.Q[e / k], sm.J[e % k]);
         for (int e = threadIdx.x - 64; e < q * s; e += NT - 64) E[e] = entry64(td.src, td.Q[e / s], td.S[e % s]);
