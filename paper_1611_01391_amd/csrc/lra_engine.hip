@@ -42,20 +42,19 @@ DI double load_elem(const void* p, int dtype, int64_t off)
 template <typename T>
 DI T kernel_entry(int kind, double d);
 
+// Branch-free: |1/d| = 1/|d| exactly (the quotient's sign is the divisor's).
 template <>
 DI double kernel_entry<double>(int kind, double d)
 {
-    if (kind == 1) return 1.0 / d;
-    double ad = fabs(d);
-    return ad == 0.0 ? 0.0 : 1.0 / ad;
+    const double r = 1.0 / d;
+    return kind == 1 ? r : (d == 0.0 ? 0.0 : fabs(r));
 }
 
 template <>
 DI float kernel_entry<float>(int kind, double d)
 {
-    if (kind == 1) return 1.0f / (float)d;
-    double ad = fabs(d);
-    return ad == 0.0 ? 0.0f : 1.0f / (float)ad;
+    const float r = 1.0f / (float)d;
+    return kind == 1 ? r : (d == 0.0 ? 0.0f : fabsf(r));
 }
 
 template <typename T>
@@ -84,6 +83,68 @@ DI T entry_t(const DevSource& s, int64_t i, int64_t j)
 }
 
 DI double entry64(const DevSource& s, int64_t i, int64_t j) { return entry_t<double>(s, i, j); }
+
+// A source's arrays are device (global) memory: global loads, unlike the
+// generic ones, do not count against the LDS wait counter.
+template <typename E>
+DI const __attribute__((address_space(1))) E* gptr(const void* p)
+{
+    return (const __attribute__((address_space(1))) E*)p;
+}
+
+// Entries (ri[n], cj[n]) of a batch, element type E of the source: every
+// load of the batch is unconditional, so all are in flight together.
+template <typename E, typename T, int N>
+DI void entries_e(const DevSource& s, const int64_t* ri, const int64_t* cj, T* out)
+{
+    if (s.kind == 0) {
+        const auto* a = gptr<E>(s.a);
+        E v[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) v[n] = a[s.col_major ? cj[n] * s.lda + ri[n] : ri[n] * s.lda + cj[n]];
+#pragma unroll
+        for (int n = 0; n < N; ++n) out[n] = (T)v[n];
+    } else {
+        const auto* x = gptr<E>(s.x);
+        const auto* y = gptr<E>(s.y);
+        E xv[N], yv[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            xv[n] = x[ri[n]];
+            yv[n] = y[cj[n]];
+        }
+#pragma unroll
+        for (int n = 0; n < N; ++n) out[n] = kernel_entry<T>(s.kind, (double)xv[n] - (double)yv[n]);
+    }
+}
+
+// Entries e in [0, total) taken by threads tid, tid + nth, ... in batches of
+// PB per thread: idx(e, i, j) names entry e, st(e, value) stores it.  The
+// source's kind and element type are uniform, so one branch on them encloses
+// a whole batch; indices past the end repeat the batch's first (valid) one,
+// so that only the stores are guarded.
+template <typename T, int PB, typename IDX, typename ST>
+DI void load_entries(const DevSource& s, int total, int tid, int nth, IDX idx, ST st)
+{
+    for (int e0 = tid; e0 < total; e0 += nth * PB) {
+        int64_t ri[PB], cj[PB];
+        T v[PB];
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            const int e = e0 + b * nth;
+            idx(e < total ? e : e0, ri[b], cj[b]);
+        }
+        if (s.dtype == 0)
+            entries_e<float, T, PB>(s, ri, cj, v);
+        else
+            entries_e<double, T, PB>(s, ri, cj, v);
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+            const int e = e0 + b * nth;
+            if (e < total) st(e, v[b]);
+        }
+    }
+}
 
 // ----------------------------------------------------------------------------
 // argmax keys: (hi, lo) compared lexicographically; hi = bit pattern of a
@@ -340,35 +401,64 @@ struct Rows {
 
 // Gather rows [r0, r0 + nrows) of the strip: column step A[:, F], row step
 // A[F, :]^T, by threads tid of nth.  Returns this thread's max |entry| (+inf
-// if an entry is not finite).
+// if an entry is not finite).  Dense sources: up to 32 columns of a row
+// loaded together, columns past k repeating column c0 so that every load is
+// unconditional.  Generated sources: 8 columns at a time (ranks grow in
+// steps of 8), from the coordinates of the index set held in LDS.
+template <typename T, int CH>
+DI double store_chunk(const T* v, int c0, int k, const Rows<T>& rw, int r, double lmax)
+{
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc) {
+        const int c = c0 + cc;
+        if (c < k) {
+            double a = fabs((double)v[cc]);
+            if (!(a <= 1.0e308)) a = INFINITY;  // NaN or Inf
+            lmax = fmax(lmax, a);
+            rw.B[c * rw.ld + r] = v[cc];
+        }
+    }
+    return lmax;
+}
+
 template <typename T, int KMAX>
 DI double gather_rows(const DevSource& s, int transpose, const Smem<T, KMAX>& sm, const int64_t* F, int k,
                       const Rows<T>& rw, int tid, int nth)
 {
-    constexpr int CH = KMAX < 32 ? KMAX : 32;  // columns loaded together
     double lmax = 0.0;
-    for (int r = tid; r < rw.nrows; r += nth) {
-        const int64_t gi = rw.r0 + r;
-        const double own = s.kind == 0 ? 0.0 : (transpose ? load_elem(s.y, s.dtype, gi) : load_elem(s.x, s.dtype, gi));
-        for (int c0 = 0; c0 < k; c0 += CH) {
-            T v[CH];
+    if (s.kind == 0) {
+        constexpr int CH = KMAX < 32 ? KMAX : 32;
+        for (int r = tid; r < rw.nrows; r += nth) {
+            const int64_t gi = rw.r0 + r;
+            for (int c0 = 0; c0 < k; c0 += CH) {
+                int64_t ri[CH], cj[CH];
+                T v[CH];
 #pragma unroll
-            for (int cc = 0; cc < CH; ++cc) {
-                const int c = c0 + cc;
-                if (c < k) {
-                    if (s.kind == 0) v[cc] = transpose ? dense_entry<T>(s, F[c], gi) : dense_entry<T>(s, gi, F[c]);
-                    else v[cc] = kernel_entry<T>(s.kind, transpose ? sm.pts[c] - own : own - sm.pts[c]);
+                for (int cc = 0; cc < CH; ++cc) {
+                    const int c = c0 + cc < k ? c0 + cc : c0;
+                    ri[cc] = transpose ? F[c] : gi;
+                    cj[cc] = transpose ? gi : F[c];
                 }
+                if (s.dtype == 0)
+                    entries_e<float, T, CH>(s, ri, cj, v);
+                else
+                    entries_e<double, T, CH>(s, ri, cj, v);
+                lmax = store_chunk<T, CH>(v, c0, k, rw, r, lmax);
             }
+        }
+    } else {
+        constexpr int CH = 8;
+        for (int r = tid; r < rw.nrows; r += nth) {
+            const int64_t gi = rw.r0 + r;
+            const double own = transpose ? load_elem(s.y, s.dtype, gi) : load_elem(s.x, s.dtype, gi);
+            for (int c0 = 0; c0 < k; c0 += CH) {
+                T v[CH];
 #pragma unroll
-            for (int cc = 0; cc < CH; ++cc) {
-                const int c = c0 + cc;
-                if (c < k) {
-                    double a = fabs((double)v[cc]);
-                    if (!(a <= 1.0e308)) a = INFINITY;  // NaN or Inf
-                    lmax = fmax(lmax, a);
-                    rw.B[c * rw.ld + r] = v[cc];
+                for (int cc = 0; cc < CH; ++cc) {
+                    const int c = c0 + cc < k ? c0 + cc : c0;
+                    v[cc] = kernel_entry<T>(s.kind, transpose ? sm.pts[c] - own : own - sm.pts[c]);
                 }
+                lmax = store_chunk<T, CH>(v, c0, k, rw, r, lmax);
             }
         }
     }
@@ -776,6 +866,20 @@ DI void lu_solve_wave0(LT* A, int k, int rhs0, int nr, Smem<T, KMAX>& sm)
         lu_aug_wave0<T, KMAX, LT, LD, NB>(A, k, rhs0, nr, sm);
 }
 
+// Pins a loaded value in straight-line code: a value used only under a
+// condition would otherwise have its load sunk into a branch of its own,
+// each with its own wait.  Pin a group of loads after issuing them all.
+DI double keep(double v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+DI float keep(float v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // ----------------------------------------------------------------------------
 // basis product on the matrix cores: slice <- slice(:, 0:kd) * W, W[d][c] at
 // W[d * wsd + c * wsc], d, c < kd.  Each wavefront owns 16-row tiles and
@@ -816,11 +920,21 @@ DI void basis_product(const Rows<T>& rw, int kd, const T* W, int wsd, int wsc)
     for (int tile = wv; tile < ntiles; tile += NWAVE) {
         const int r = tile * 16 + (lane & 15);
         const bool rok = r < rw.nrows;
+        // loads at clamped (in-bounds) indices, all issued before they are
+        // pinned, zero selected outside: no per-load branch or wait
+        const int rc = rok ? r : 0;
         T a[KB];
 #pragma unroll
         for (int kb = 0; kb < KB; ++kb) {
             const int d = kb * 4 + (lane >> 4);
-            a[kb] = (kb < kbn && rok && d < kd) ? rw.B[d * rw.ld + r] : (T)0;
+            a[kb] = rw.B[(d < kd ? d : 0) * rw.ld + rc];
+        }
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) a[kb] = keep(a[kb]);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            const int d = kb * 4 + (lane >> 4);
+            a[kb] = (kb < kbn && rok && d < kd) ? a[kb] : (T)0;
         }
         acc_t out[CT];
 #pragma unroll
@@ -828,14 +942,22 @@ DI void basis_product(const Rows<T>& rw, int kd, const T* W, int wsd, int wsc)
             acc_t acc = {0, 0, 0, 0};
             if (ct < ctn) {
                 const int c = ct * 16 + (lane & 15);
+                T w[KB];
 #pragma unroll
                 for (int kb = 0; kb < KB; ++kb) {
-                    if (kb < kbn) {
-                        const int d = kb * 4 + (lane >> 4);
-                        const T w = (d < kd && c < kd) ? W[d * wsd + c * wsc] : (T)0;
-                        acc = mfma16(a[kb], w, acc);
-                    }
+                    const int d = kb * 4 + (lane >> 4);
+                    w[kb] = W[(d < kd ? d : 0) * wsd + (c < kd ? c : 0) * wsc];
                 }
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) w[kb] = keep(w[kb]);
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) {
+                    const int d = kb * 4 + (lane >> 4);
+                    w[kb] = (d < kd && c < kd) ? w[kb] : (T)0;
+                }
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb)
+                    if (kb < kbn) acc = mfma16(a[kb], w[kb], acc);
             }
             out[ct] = acc;
         }
@@ -922,26 +1044,20 @@ DI void warm_load(const TaskDesc& td, Smem<T, KMAX>& sm, int transpose)
     const int64_t* X = transpose ? sm.J : sm.I;
     constexpr int LD = 2 * KMAX;
     T* AUG = (T*)sm.AUG;
-    // M[c][s] = strip(X[s], c); all loads issued before the stores
-    constexpr int PER = (KMAX * KMAX + NT - 1) / NT;
-    T mv[PER];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int e = threadIdx.x + i * NT;
-        if (e < k * k) {
+    // M[c][s] = strip(X[s], c)
+    const int kk = k * k;
+    load_entries<T, (KMAX * KMAX + NT - 1) / NT>(
+        td.src, kk, threadIdx.x, NT,
+        [&](int e, int64_t& i, int64_t& j) {
             const int c = e / k, s2 = e % k;
-            mv[i] = transpose ? entry_t<T>(td.src, F[c], X[s2]) : entry_t<T>(td.src, X[s2], F[c]);
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int e = threadIdx.x + i * NT;
-        if (e < k * k) {
+            i = transpose ? F[c] : X[s2];
+            j = transpose ? X[s2] : F[c];
+        },
+        [&](int e, T v) {
             const int c = e / k, s2 = e % k;
-            AUG[c * LD + s2] = mv[i];
+            AUG[c * LD + s2] = v;
             AUG[c * LD + KMAX + s2] = (T)(c == s2 ? 1 : 0);
-        }
-    }
+        });
 }
 
 // Gather this workgroup's rows of the strip and return the team-wide max
@@ -1350,14 +1466,25 @@ DI void final_core(const TaskDesc& td, Team& tio)
     double* Fm = FLDS ? (double*)blds_ptr<T, KMAX>() : td.work;
     double* AQJ = Fm + (int64_t)KMAX * LDF;
     double* E = AQJ + (int64_t)q * k;
-    for (int e = threadIdx.x; e < k * k; e += NT) {
-        const int a = e / k, t = e % k;
-        const double v = entry64(td.src, sm.I[a], sm.J[t]);
-        Fm[a * LDF + t] = v;
-        Fm[a * LDF + KMAX + t] = a == t ? 1.0 : 0.0;
-        td.G[e] = v;
-    }
-    for (int e = threadIdx.x; e < k * s; e += NT) Fm[(e / s) * LDF + KMAX + k + e % s] = entry64(td.src, sm.I[e / s], td.S[e % s]);
+    load_entries<double, 8>(
+        td.src, k * k, threadIdx.x, NT,
+        [&](int e, int64_t& i, int64_t& j) {
+            i = sm.I[e / k];
+            j = sm.J[e % k];
+        },
+        [&](int e, double v) {
+            const int a = e / k, t = e % k;
+            Fm[a * LDF + t] = v;
+            Fm[a * LDF + KMAX + t] = a == t ? 1.0 : 0.0;
+            td.G[e] = v;
+        });
+    load_entries<double, 8>(
+        td.src, k * s, threadIdx.x, NT,
+        [&](int e, int64_t& i, int64_t& j) {
+            i = sm.I[e / s];
+            j = td.S[e % s];
+        },
+        [&](int e, double v) { Fm[(e / s) * LDF + KMAX + k + e % s] = v; });
     __threadfence_block();
     __syncthreads();
     // ||G||_1 before the factorisation overwrites G
@@ -1371,8 +1498,20 @@ DI void final_core(const TaskDesc& td, Team& tio)
     if (threadIdx.x < 64) {
         lu_solve_wave0<T, KMAX, double, LDF, (2 * KMAX + 127) / 64, 2>(Fm, k, KMAX, k + s, sm);
     } else {
-        for (int e = threadIdx.x - 64; e < q * k; e += NT - 64) AQJ[e] = entry64(td.src, td.Q[e / k], sm.J[e % k]);
-        for (int e = threadIdx.x - 64; e < q * s; e += NT - 64) E[e] = entry64(td.src, td.Q[e / s], td.S[e % s]);
+        load_entries<double, 8>(
+            td.src, q * k, threadIdx.x - 64, NT - 64,
+            [&](int e, int64_t& i, int64_t& j) {
+                i = td.Q[e / k];
+                j = sm.J[e % k];
+            },
+            [&](int e, double v) { AQJ[e] = v; });
+        load_entries<double, 8>(
+            td.src, q * s, threadIdx.x - 64, NT - 64,
+            [&](int e, int64_t& i, int64_t& j) {
+                i = td.Q[e / s];
+                j = td.S[e % s];
+            },
+            [&](int e, double v) { E[e] = v; });
     }
     __threadfence_block();
     __syncthreads();

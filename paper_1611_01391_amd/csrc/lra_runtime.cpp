@@ -131,7 +131,7 @@ struct lra_ctx {
     std::map<std::string, int> tuned;  // autotuned team sizes by size class
     int64_t floor_rows = -1;           // autotuned planning floor (-1: default)
     bool timing = false;
-    bool trace = false;
+    int trace = 0;  // LRA_TRACE: 1 summary, 2 also every event
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     lra_stats stats{};
     Serve* srv = nullptr;    // serving scheduler, created by the first serving call
@@ -224,7 +224,7 @@ extern "C" lra_status lra_create(lra_ctx** out, void* stream, size_t budget)
     if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && rate > 0)
         c->wall_rate_khz = rate;
     if (const char* t = std::getenv("LRA_TIMEOUT_S")) c->timeout_s = std::atof(t);
-    if (const char* t = std::getenv("LRA_TRACE")) c->trace = std::atoi(t) != 0;
+    if (const char* t = std::getenv("LRA_TRACE")) c->trace = std::atoi(t);
     // LDS for strip rows: all the device leaves per workgroup after the fixed
     // part of each kernel variant (LRA_LDS_B_BYTES caps it)
     int static_lds = 0;
@@ -672,6 +672,9 @@ static void dump_trace(lra_ctx* ctx, const uint64_t* tr, int cap)
         const int ev = (int)(tr[1 + 2 * i] >> 56);
         const double dt = (double)(tr[2 + 2 * i] - tr[2 + 2 * (i - 1)]) * us_per_tick;
         if (ev > 0 && ev < 14) { tot[ev] += dt; cnt[ev] += 1; }
+        if (ctx->trace >= 2 && ev > 0 && ev < 14)
+            std::fprintf(stderr, "[lra trace] %5llu %-12s arg %6lld  +%8.2f us\n", (unsigned long long)i, names[ev],
+                         (long long)(tr[1 + 2 * i] & 0x00FFFFFFFFFFFFFFull), dt);
     }
     std::fprintf(stderr, "[lra trace] %llu events\n", (unsigned long long)n);
     for (int e = 1; e < 14; ++e)
