@@ -84,12 +84,20 @@ DI T entry_t(const DevSource& s, int64_t i, int64_t j)
 
 DI double entry64(const DevSource& s, int64_t i, int64_t j) { return entry_t<double>(s, i, j); }
 
-// A source's arrays are device (global) memory: global loads, unlike the
-// generic ones, do not count against the LDS wait counter.
-template <typename E>
-DI const __attribute__((address_space(1))) E* gptr(const void* p)
+// Device allocations (sources, descriptors' arrays, control blocks, trace)
+// are accessed through global-address-space pointers: generic (flat)
+// accesses also count against the LDS wait counter, so that every wait for
+// an LDS value would wait for them too.  Never for LDS or stack objects.
+#define GL __attribute__((address_space(1)))
+template <typename T>
+DI GL T* gl(T* p)
 {
-    return (const __attribute__((address_space(1))) E*)p;
+    return (GL T*)p;
+}
+template <typename E>
+DI const GL E* gptr(const void* p)
+{
+    return (const GL E*)p;
 }
 
 // Entries (ri[n], cj[n]) of a batch, element type E of the source: every
@@ -276,9 +284,10 @@ DI void trace_ev(Team& tm, int ev, int64_t arg)
     if (tm.trace == nullptr || tm.rank != 0 || threadIdx.x != 0) return;
     const int idx = tm.trace_n++;
     if (idx >= tm.trace_cap) return;
-    tm.trace[1 + 2 * idx] = ((uint64_t)ev << 56) | ((uint64_t)arg & 0x00FFFFFFFFFFFFFFull);
-    tm.trace[2 + 2 * idx] = wall_clock64();
-    tm.trace[0] = (uint64_t)(idx + 1);
+    GL uint64_t* tr = gl(tm.trace);
+    tr[1 + 2 * idx] = ((uint64_t)ev << 56) | ((uint64_t)arg & 0x00FFFFFFFFFFFFFFull);
+    tr[2 + 2 * idx] = wall_clock64();
+    tr[0] = (uint64_t)(idx + 1);
 }
 
 // ----------------------------------------------------------------------------
@@ -288,9 +297,9 @@ DI void trace_ev(Team& tm, int ev, int64_t arg)
 // other workgroups' data visible.
 // ----------------------------------------------------------------------------
 
-DI uint8_t* slot_ptr(const Team& tm, int parity, int wg)
+DI GL uint8_t* slot_ptr(const Team& tm, int parity, int wg)
 {
-    return tm.ctl + CTL_HDR + (int64_t)(parity * tm.size + wg) * SLOT_STRIDE;
+    return gl(tm.ctl) + CTL_HDR + (int64_t)(parity * tm.size + wg) * SLOT_STRIDE;
 }
 
 DI int32_t* lds_flag();
@@ -299,7 +308,7 @@ DI void team_barrier(Team& tm)
 {
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t* ctr = (uint32_t*)tm.ctl;
+        GL uint32_t* ctr = (GL uint32_t*)gl(tm.ctl);
         __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, AGENT);
         const uint32_t target = (tm.epoch + 1) * (uint32_t)tm.size;
         const int64_t t0 = wall_clock64();
@@ -309,7 +318,7 @@ DI void team_barrier(Team& tm)
         for (uint32_t spins = 1; __hip_atomic_load(ctr, __ATOMIC_RELAXED, AGENT) < target; ++spins) {
             __builtin_amdgcn_s_sleep(1);
             if ((spins & 63) == 0 && wall_clock64() - t0 > tm.timeout) {
-                atomicOr(tm.err, 1u);
+                __hip_atomic_fetch_or(gl(tm.err), 1u, __ATOMIC_RELAXED, AGENT);
                 bad = 1;
                 break;
             }
@@ -337,28 +346,28 @@ DI K2 team_argmax(Team& tm, Smem<T, KMAX>& sm, const K2& mine, int n, int64_t ro
     const int par = tm.xepoch & 1;
     const uint32_t stamp = tm.xepoch + 1;
     tm.xepoch = stamp;
-    uint8_t* my = slot_ptr(tm, par, tm.rank);
-    double* mypay = (double*)(my + 32);
+    GL uint8_t* my = slot_ptr(tm, par, tm.rank);
+    GL double* mypay = (GL double*)(my + 32);
     // written by wavefront 0 only: its release below orders all of them
     if (threadIdx.x < n)
         __hip_atomic_store(mypay + threadIdx.x, (double)sm.pay[threadIdx.x], __ATOMIC_RELAXED, AGENT);
     if (threadIdx.x == 0) {
-        __hip_atomic_store((uint64_t*)my, mine.hi, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store((uint64_t*)(my + 8), mine.lo, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store((uint32_t*)(my + 16), stamp, __ATOMIC_RELEASE, AGENT);
+        __hip_atomic_store((GL uint64_t*)my, mine.hi, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store((GL uint64_t*)(my + 8), mine.lo, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store((GL uint32_t*)(my + 16), stamp, __ATOMIC_RELEASE, AGENT);
     }
     // a slot that never arrives yields the reserved key K2_FAIL, which wins
     // the reduction (keys of moduli, +inf included, have smaller hi words)
     K2 o = k2_none();
     if (threadIdx.x < tm.size) {
-        const uint8_t* sp = slot_ptr(tm, par, threadIdx.x);
+        const GL uint8_t* sp = slot_ptr(tm, par, threadIdx.x);
         const int64_t t0 = wall_clock64();
         bool bad = false;
-        for (uint32_t spins = 1; __hip_atomic_load((const uint32_t*)(sp + 16), __ATOMIC_RELAXED, AGENT) != stamp;
+        for (uint32_t spins = 1; __hip_atomic_load((const GL uint32_t*)(sp + 16), __ATOMIC_RELAXED, AGENT) != stamp;
              ++spins) {
             __builtin_amdgcn_s_sleep(1);
             if ((spins & 63) == 0 && wall_clock64() - t0 > tm.timeout) {
-                atomicOr(tm.err, 1u);
+                __hip_atomic_fetch_or(gl(tm.err), 1u, __ATOMIC_RELAXED, AGENT);
                 bad = true;
                 break;
             }
@@ -367,8 +376,8 @@ DI K2 team_argmax(Team& tm, Smem<T, KMAX>& sm, const K2& mine, int n, int64_t ro
         if (bad) {
             o = K2{~0ull, ~0ull};
         } else {
-            o.hi = __hip_atomic_load((const uint64_t*)sp, __ATOMIC_RELAXED, AGENT);
-            o.lo = __hip_atomic_load((const uint64_t*)(sp + 8), __ATOMIC_RELAXED, AGENT);
+            o.hi = __hip_atomic_load((const GL uint64_t*)sp, __ATOMIC_RELAXED, AGENT);
+            o.lo = __hip_atomic_load((const GL uint64_t*)(sp + 8), __ATOMIC_RELAXED, AGENT);
         }
     }
     const K2 best = block_argmax(o, sm, tm);
@@ -379,7 +388,7 @@ DI K2 team_argmax(Team& tm, Smem<T, KMAX>& sm, const K2& mine, int n, int64_t ro
     if (n > 0) {
         const int w = (int)(k2_row(best) / rows_per_wg);
         if (threadIdx.x < n) {
-            const double* wp = (const double*)(slot_ptr(tm, par, w) + 32);
+            const GL double* wp = (const GL double*)(slot_ptr(tm, par, w) + 32);
             sm.pay[threadIdx.x] = (T)__hip_atomic_load(wp + threadIdx.x, __ATOMIC_RELAXED, AGENT);
         }
         __syncthreads();
@@ -422,9 +431,10 @@ DI double store_chunk(const T* v, int c0, int k, const Rows<T>& rw, int r, doubl
 }
 
 template <typename T, int KMAX>
-DI double gather_rows(const DevSource& s, int transpose, const Smem<T, KMAX>& sm, const int64_t* F, int k,
+DI double gather_rows(const DevSource& src, int transpose, const Smem<T, KMAX>& sm, const int64_t* F, int k,
                       const Rows<T>& rw, int tid, int nth)
 {
+    const DevSource s = src;  // read once: stores to a global strip could alias it
     double lmax = 0.0;
     if (s.kind == 0) {
         constexpr int CH = KMAX < 32 ? KMAX : 32;
@@ -1404,6 +1414,7 @@ DI void maxvol_dispatch(const TaskDesc& td, Team& tm, int transpose, int lds_b_b
     Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
     const int64_t M = transpose ? td.n : td.m;
     const int64_t R = (M + tm.size - 1) / tm.size;
+    trace_ev(tm, EV_DISPATCH, transpose);
     if (R * sm.k * (int64_t)sizeof(T) <= lds_b_bytes) maxvol_step<T, KMAX, true>(td, tm, transpose);
     else maxvol_step<T, KMAX, false>(td, tm, transpose);
 }
@@ -1416,19 +1427,40 @@ template <typename T, int KMAX>
 NOINL void write_factors(const TaskDesc& td, Smem<T, KMAX>& sm, const Team& tm)
 {
     const int k = sm.k;
-    if (td.C_out) {
-        T* C = (T*)td.C_out;
-        const int64_t R = (td.m + tm.size - 1) / tm.size;
-        const int64_t a = (int64_t)tm.rank * R, b = a + R < td.m ? a + R : td.m;
-        for (int64_t i = a + threadIdx.x; i < b; i += NT)
-            for (int c = 0; c < k; ++c) C[c * td.m + i] = entry_t<T>(td.src, i, sm.J[c]);
+    // descriptor fields read once, before any store (a store could alias them)
+    const DevSource src = td.src;
+    const int64_t m = td.m, n = td.n;
+    GL T* const C = (GL T*)td.C_out;
+    GL T* const Rm = (GL T*)td.R_out;
+    if (C) {
+        const int64_t R = (m + tm.size - 1) / tm.size;
+        const int64_t a = (int64_t)tm.rank * R, b = a + R < m ? a + R : m;
+        const int rows = b > a ? (int)(b - a) : 0;
+        for (int c = 0; c < k; ++c) {
+            const int64_t jc = sm.J[c];
+            load_entries<T, 8>(
+                src, rows, threadIdx.x, NT,
+                [&](int e, int64_t& i, int64_t& j) {
+                    i = a + e;
+                    j = jc;
+                },
+                [&](int e, T v) { C[c * m + a + e] = v; });
+        }
     }
-    if (td.R_out) {
-        T* Rm = (T*)td.R_out;
-        const int64_t R = (td.n + tm.size - 1) / tm.size;
-        const int64_t a = (int64_t)tm.rank * R, b = a + R < td.n ? a + R : td.n;
-        for (int c = 0; c < k; ++c)
-            for (int64_t j = a + threadIdx.x; j < b; j += NT) Rm[c * td.n + j] = entry_t<T>(td.src, sm.I[c], j);
+    if (Rm) {
+        const int64_t R = (n + tm.size - 1) / tm.size;
+        const int64_t a = (int64_t)tm.rank * R, b = a + R < n ? a + R : n;
+        const int cols = b > a ? (int)(b - a) : 0;
+        for (int c = 0; c < k; ++c) {
+            const int64_t ic = sm.I[c];
+            load_entries<T, 8>(
+                src, cols, threadIdx.x, NT,
+                [&](int e, int64_t& i, int64_t& j) {
+                    i = ic;
+                    j = a + e;
+                },
+                [&](int e, T v) { Rm[c * n + a + e] = v; });
+        }
     }
 }
 
@@ -1461,13 +1493,19 @@ DI void final_core(const TaskDesc& td, Team& tio)
     Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
     const int k = sm.k;
     const int q = td.q, s = td.s;
+    // descriptor fields read once, before any store (a store could alias them)
+    GL double* const Gout = gl(td.G);
+    GL double* const Uout = gl(td.U);
+    const GL int64_t* const Qi = gl(td.Q);
+    const GL int64_t* const Si = gl(td.S);
+    const DevSource src = td.src;
     // F = [G | I | A[I,S]] (row stride LDF; s <= 64), then A[Q,J] and A[Q,S]
     constexpr int LDF = 2 * KMAX + 64;
     double* Fm = FLDS ? (double*)blds_ptr<T, KMAX>() : td.work;
     double* AQJ = Fm + (int64_t)KMAX * LDF;
     double* E = AQJ + (int64_t)q * k;
     load_entries<double, 8>(
-        td.src, k * k, threadIdx.x, NT,
+        src, k * k, threadIdx.x, NT,
         [&](int e, int64_t& i, int64_t& j) {
             i = sm.I[e / k];
             j = sm.J[e % k];
@@ -1476,13 +1514,13 @@ DI void final_core(const TaskDesc& td, Team& tio)
             const int a = e / k, t = e % k;
             Fm[a * LDF + t] = v;
             Fm[a * LDF + KMAX + t] = a == t ? 1.0 : 0.0;
-            td.G[e] = v;
+            Gout[e] = v;
         });
     load_entries<double, 8>(
-        td.src, k * s, threadIdx.x, NT,
+        src, k * s, threadIdx.x, NT,
         [&](int e, int64_t& i, int64_t& j) {
             i = sm.I[e / s];
-            j = td.S[e % s];
+            j = Si[e % s];
         },
         [&](int e, double v) { Fm[(e / s) * LDF + KMAX + k + e % s] = v; });
     __threadfence_block();
@@ -1499,17 +1537,17 @@ DI void final_core(const TaskDesc& td, Team& tio)
         lu_solve_wave0<T, KMAX, double, LDF, (2 * KMAX + 127) / 64, 2>(Fm, k, KMAX, k + s, sm);
     } else {
         load_entries<double, 8>(
-            td.src, q * k, threadIdx.x - 64, NT - 64,
+            src, q * k, threadIdx.x - 64, NT - 64,
             [&](int e, int64_t& i, int64_t& j) {
-                i = td.Q[e / k];
+                i = Qi[e / k];
                 j = sm.J[e % k];
             },
             [&](int e, double v) { AQJ[e] = v; });
         load_entries<double, 8>(
-            td.src, q * s, threadIdx.x - 64, NT - 64,
+            src, q * s, threadIdx.x - 64, NT - 64,
             [&](int e, int64_t& i, int64_t& j) {
-                i = td.Q[e / s];
-                j = td.S[e % s];
+                i = Qi[e / s];
+                j = Si[e % s];
             },
             [&](int e, double v) { E[e] = v; });
     }
@@ -1523,7 +1561,7 @@ DI void final_core(const TaskDesc& td, Team& tio)
     }
     __threadfence_block();
     __syncthreads();
-    for (int e = threadIdx.x; e < k * k; e += NT) td.U[e] = Fm[(e / k) * LDF + KMAX + e % k];
+    for (int e = threadIdx.x; e < k * k; e += NT) Uout[e] = Fm[(e / k) * LDF + KMAX + e % k];
     const double* W = Fm + KMAX + k;  // W[t][b] at W[t * LDF + b]
     double cu = 0.0;
     if (threadIdx.x < k)
@@ -1575,7 +1613,7 @@ DI void final_core(const TaskDesc& td, Team& tio)
             const int room = td.kmax - k < td.kstep ? td.kmax - k : td.kstep;
             int added = 0;
             while (added < room && sm.cand_next < td.n_cand) {
-                const int64_t cnd = td.cand[sm.cand_next++];
+                const int64_t cnd = gl(td.cand)[sm.cand_next++];
                 int dup = 0;
                 for (int c = 0; c < k + added; ++c)
                     if (sm.J[c] == cnd) { dup = 1; break; }
@@ -1610,72 +1648,120 @@ NOINL void final_leader(const TaskDesc& td, Team& tio, int lds_b_bytes)
 // ----------------------------------------------------------------------------
 
 template <typename T, int KMAX>
-NOINL void load_state(const TaskDesc& td, Smem<T, KMAX>& sm)
+DI void load_state(const TaskDesc& td, Smem<T, KMAX>& sm)
 {
+    // all loads first, then the LDS writes: one memory round trip
     if (threadIdx.x == 0) {
-        const TaskState* st = td.st;
-        sm.phase = __hip_atomic_load(&st->phase, __ATOMIC_RELAXED, AGENT);
-        sm.k = __hip_atomic_load(&st->k, __ATOMIC_RELAXED, AGENT);
-        sm.sweep_in_level = __hip_atomic_load(&st->sweep_in_level, __ATOMIC_RELAXED, AGENT);
-        sm.status = __hip_atomic_load(&st->status, __ATOMIC_RELAXED, AGENT);
-        sm.warn = __hip_atomic_load(&st->warn, __ATOMIC_RELAXED, AGENT);
-        sm.have_I = __hip_atomic_load(&st->have_I, __ATOMIC_RELAXED, AGENT);
-        sm.had_I_sweep = __hip_atomic_load(&st->had_I_sweep, __ATOMIC_RELAXED, AGENT);
-        sm.k_sweep_start = __hip_atomic_load(&st->k_sweep_start, __ATOMIC_RELAXED, AGENT);
-        sm.swaps_total = __hip_atomic_load(&st->swaps_total, __ATOMIC_RELAXED, AGENT);
-        sm.sweeps_done = __hip_atomic_load(&st->sweeps_done, __ATOMIC_RELAXED, AGENT);
-        sm.phases_run = __hip_atomic_load(&st->phases_run, __ATOMIC_RELAXED, AGENT);
-        sm.cand_next = __hip_atomic_load(&st->cand_next, __ATOMIC_RELAXED, AGENT);
-        sm.entries_read = __hip_atomic_load(&st->entries_read, __ATOMIC_RELAXED, AGENT);
-        sm.est_rel = __hip_atomic_load(&st->est_rel, __ATOMIC_RELAXED, AGENT);
-        sm.est_abs = __hip_atomic_load(&st->est_abs, __ATOMIC_RELAXED, AGENT);
-        sm.mean = __hip_atomic_load(&st->mean, __ATOMIC_RELAXED, AGENT);
-        sm.var = __hip_atomic_load(&st->var, __ATOMIC_RELAXED, AGENT);
-        sm.cond1 = __hip_atomic_load(&st->cond1, __ATOMIC_RELAXED, AGENT);
+        const GL TaskState* st = gl(td.st);
+        const int32_t phase = __hip_atomic_load(&st->phase, __ATOMIC_RELAXED, AGENT);
+        const int32_t k = __hip_atomic_load(&st->k, __ATOMIC_RELAXED, AGENT);
+        const int32_t sweep_in_level = __hip_atomic_load(&st->sweep_in_level, __ATOMIC_RELAXED, AGENT);
+        const int32_t status = __hip_atomic_load(&st->status, __ATOMIC_RELAXED, AGENT);
+        const int32_t warn = __hip_atomic_load(&st->warn, __ATOMIC_RELAXED, AGENT);
+        const int32_t have_I = __hip_atomic_load(&st->have_I, __ATOMIC_RELAXED, AGENT);
+        const int32_t had_I_sweep = __hip_atomic_load(&st->had_I_sweep, __ATOMIC_RELAXED, AGENT);
+        const int32_t k_sweep_start = __hip_atomic_load(&st->k_sweep_start, __ATOMIC_RELAXED, AGENT);
+        const int32_t swaps_total = __hip_atomic_load(&st->swaps_total, __ATOMIC_RELAXED, AGENT);
+        const int32_t sweeps_done = __hip_atomic_load(&st->sweeps_done, __ATOMIC_RELAXED, AGENT);
+        const int32_t phases_run = __hip_atomic_load(&st->phases_run, __ATOMIC_RELAXED, AGENT);
+        const int64_t cand_next = __hip_atomic_load(&st->cand_next, __ATOMIC_RELAXED, AGENT);
+        const int64_t entries_read = __hip_atomic_load(&st->entries_read, __ATOMIC_RELAXED, AGENT);
+        const double est_rel = __hip_atomic_load(&st->est_rel, __ATOMIC_RELAXED, AGENT);
+        const double est_abs = __hip_atomic_load(&st->est_abs, __ATOMIC_RELAXED, AGENT);
+        const double mean = __hip_atomic_load(&st->mean, __ATOMIC_RELAXED, AGENT);
+        const double var = __hip_atomic_load(&st->var, __ATOMIC_RELAXED, AGENT);
+        const double cond1 = __hip_atomic_load(&st->cond1, __ATOMIC_RELAXED, AGENT);
+        sm.phase = phase;
+        sm.k = k;
+        sm.sweep_in_level = sweep_in_level;
+        sm.status = status;
+        sm.warn = warn;
+        sm.have_I = have_I;
+        sm.had_I_sweep = had_I_sweep;
+        sm.k_sweep_start = k_sweep_start;
+        sm.swaps_total = swaps_total;
+        sm.sweeps_done = sweeps_done;
+        sm.phases_run = phases_run;
+        sm.cand_next = cand_next;
+        sm.entries_read = entries_read;
+        sm.est_rel = est_rel;
+        sm.est_abs = est_abs;
+        sm.mean = mean;
+        sm.var = var;
+        sm.cond1 = cond1;
     }
     const int kc = td.kmax > td.k0 ? td.kmax : td.k0;
     if (threadIdx.x < kc) {
         const int c = threadIdx.x;
-        sm.I[c] = __hip_atomic_load(td.I + c, __ATOMIC_RELAXED, AGENT);
-        sm.J[c] = __hip_atomic_load(td.J + c, __ATOMIC_RELAXED, AGENT);
-        sm.prevI[c] = __hip_atomic_load(td.prevI + c, __ATOMIC_RELAXED, AGENT);
-        sm.prevJ[c] = __hip_atomic_load(td.prevJ + c, __ATOMIC_RELAXED, AGENT);
+        const int64_t vi = __hip_atomic_load(gl(td.I) + c, __ATOMIC_RELAXED, AGENT);
+        const int64_t vj = __hip_atomic_load(gl(td.J) + c, __ATOMIC_RELAXED, AGENT);
+        const int64_t pi = __hip_atomic_load(gl(td.prevI) + c, __ATOMIC_RELAXED, AGENT);
+        const int64_t pj = __hip_atomic_load(gl(td.prevJ) + c, __ATOMIC_RELAXED, AGENT);
+        sm.I[c] = vi;
+        sm.J[c] = vj;
+        sm.prevI[c] = pi;
+        sm.prevJ[c] = pj;
     }
     __syncthreads();
 }
 
 // Written by wavefront 0 only (see the team synchronisation notes).
 template <typename T, int KMAX>
-NOINL void store_state(const TaskDesc& td, Smem<T, KMAX>& sm)
+DI void store_state(const TaskDesc& td, Smem<T, KMAX>& sm)
 {
+    // descriptor fields read before any store (a store could alias them)
+    GL int64_t* const I = gl(td.I);
+    GL int64_t* const J = gl(td.J);
+    GL int64_t* const pI = gl(td.prevI);
+    GL int64_t* const pJ = gl(td.prevJ);
+    GL TaskState* const st = gl(td.st);
     const int kc = td.kmax > td.k0 ? td.kmax : td.k0;
     if (threadIdx.x < kc) {
         const int c = threadIdx.x;
-        __hip_atomic_store(td.I + c, sm.I[c], __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(td.J + c, sm.J[c], __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(td.prevI + c, sm.prevI[c], __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(td.prevJ + c, sm.prevJ[c], __ATOMIC_RELAXED, AGENT);
+        const int64_t vi = sm.I[c], vj = sm.J[c], pi = sm.prevI[c], pj = sm.prevJ[c];
+        __hip_atomic_store(I + c, vi, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(J + c, vj, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(pI + c, pi, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(pJ + c, pj, __ATOMIC_RELAXED, AGENT);
     }
     if (threadIdx.x == 0) {
-        TaskState* st = td.st;
-        __hip_atomic_store(&st->phase, sm.phase, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->k, sm.k, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->sweep_in_level, sm.sweep_in_level, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->status, sm.status, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->warn, sm.warn, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->have_I, sm.have_I, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->had_I_sweep, sm.had_I_sweep, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->k_sweep_start, sm.k_sweep_start, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->swaps_total, sm.swaps_total, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->sweeps_done, sm.sweeps_done, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->phases_run, sm.phases_run, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->cand_next, sm.cand_next, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->entries_read, sm.entries_read, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->est_rel, sm.est_rel, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->est_abs, sm.est_abs, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->mean, sm.mean, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->var, sm.var, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store(&st->cond1, sm.cond1, __ATOMIC_RELAXED, AGENT);
+        TaskState v;
+        v.phase = sm.phase;
+        v.k = sm.k;
+        v.sweep_in_level = sm.sweep_in_level;
+        v.status = sm.status;
+        v.warn = sm.warn;
+        v.have_I = sm.have_I;
+        v.had_I_sweep = sm.had_I_sweep;
+        v.k_sweep_start = sm.k_sweep_start;
+        v.swaps_total = sm.swaps_total;
+        v.sweeps_done = sm.sweeps_done;
+        v.cand_next = sm.cand_next;
+        v.entries_read = sm.entries_read;
+        v.est_rel = sm.est_rel;
+        v.est_abs = sm.est_abs;
+        v.mean = sm.mean;
+        v.var = sm.var;
+        v.cond1 = sm.cond1;
+        v.phases_run = sm.phases_run;
+        __hip_atomic_store(&st->phase, v.phase, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->k, v.k, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->sweep_in_level, v.sweep_in_level, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->status, v.status, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->warn, v.warn, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->have_I, v.have_I, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->had_I_sweep, v.had_I_sweep, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->k_sweep_start, v.k_sweep_start, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->swaps_total, v.swaps_total, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->sweeps_done, v.sweeps_done, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->phases_run, v.phases_run, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->cand_next, v.cand_next, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->entries_read, v.entries_read, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->est_rel, v.est_rel, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->est_abs, v.est_abs, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->mean, v.mean, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->var, v.var, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->cond1, v.cond1, __ATOMIC_RELAXED, AGENT);
     }
 }
 
@@ -1739,6 +1825,7 @@ DI void run_task(const TaskDesc& td, Team& tm, const EngineArgs& ea)
         if (threadIdx.x == 0) sm.phases_run += 1;
         __syncthreads();
         if (tm.rank == 0) store_state(td, sm);
+        trace_ev(tm, EV_PHASE_END, sm.phase);
     }
 }
 
@@ -1749,7 +1836,7 @@ DI void run_task(const TaskDesc& td, Team& tm, const EngineArgs& ea)
 template <typename RUN>
 DI void engine_loop(const EngineArgs& ea, RUN run)
 {
-    const int team = ea.wg_team[blockIdx.x];
+    const int team = gl(ea.wg_team)[blockIdx.x];
     const TeamInfo ti = ea.teams[team];
     Team tm;
     tm.ctl = ea.team_ctl + (int64_t)team * ea.team_ctl_stride;
@@ -1766,9 +1853,9 @@ DI void engine_loop(const EngineArgs& ea, RUN run)
     tm.trace_n = 0;
     for (;;) {
         const int par = tm.epoch & 1;
-        int32_t* fetch = (int32_t*)(tm.ctl + 64) + par;
+        GL int32_t* fetch = (GL int32_t*)gl(tm.ctl + 64) + par;
         if (threadIdx.x == 0 && tm.rank == 0) {
-            const int idx = (int)atomicAdd(ea.queue_head + ti.queue, 1u);
+            const int idx = (int)__hip_atomic_fetch_add(gl(ea.queue_head) + ti.queue, 1u, __ATOMIC_RELAXED, AGENT);
             *lds_fetch() = idx;
             if (tm.size > 1) __hip_atomic_store(fetch, idx, __ATOMIC_RELAXED, AGENT);
         }
@@ -1780,8 +1867,8 @@ DI void engine_loop(const EngineArgs& ea, RUN run)
         __syncthreads();
         const int idx = *lds_fetch();
         __syncthreads();
-        if (idx >= ea.queue_len[ti.queue]) break;
-        const int task = ea.queue_items[ea.queue_off[ti.queue] + idx];
+        if (idx >= gl(ea.queue_len)[ti.queue]) break;
+        const int task = gl(ea.queue_items)[gl(ea.queue_off)[ti.queue] + idx];
         trace_ev(tm, EV_TASK_BEGIN, task);
         run(ea.tasks[task], tm);
         trace_ev(tm, EV_TASK_END, task);

@@ -103,7 +103,7 @@ struct EngineArgs {
 enum TraceEv : int32_t {
     EV_STEP_BEGIN = 1, EV_WARM_LU = 2, EV_GATHERED = 3, EV_BASIS = 4, EV_SWAP = 5, EV_STEP_END = 6,
     EV_FINAL_BEGIN = 7, EV_FINAL_END = 8, EV_TASK_BEGIN = 9, EV_TASK_END = 10, EV_PIVOT = 11,
-    EV_SWAP_RED = 12, EV_SWAP_XCH = 13
+    EV_SWAP_RED = 12, EV_SWAP_XCH = 13, EV_PHASE_END = 14, EV_DISPATCH = 15
 };
 
 // Team control block layout: [0, 64): barrier counter; [64, 72): fetched task

@@ -663,21 +663,21 @@ static void dump_trace(lra_ctx* ctx, const uint64_t* tr, int cap)
 {
     static const char* names[] = {"?", "step_begin", "warm_lu", "gathered", "basis", "swap_g",
                                   "step_end", "final_begin", "final_end", "task_begin", "task_end",
-                                  "pivot", "swap_upd+red", "swap_xchg"};
+                                  "pivot", "swap_upd+red", "swap_xchg", "phase_end", "dispatch"};
     const uint64_t n = std::min<uint64_t>(tr[0], (uint64_t)cap);
-    double tot[14] = {0};
-    int64_t cnt[14] = {0};
+    double tot[16] = {0};
+    int64_t cnt[16] = {0};
     const double us_per_tick = 1000.0 / (double)ctx->wall_rate_khz;
     for (uint64_t i = 1; i < n; ++i) {
         const int ev = (int)(tr[1 + 2 * i] >> 56);
         const double dt = (double)(tr[2 + 2 * i] - tr[2 + 2 * (i - 1)]) * us_per_tick;
-        if (ev > 0 && ev < 14) { tot[ev] += dt; cnt[ev] += 1; }
-        if (ctx->trace >= 2 && ev > 0 && ev < 14)
+        if (ev > 0 && ev < 16) { tot[ev] += dt; cnt[ev] += 1; }
+        if (ctx->trace >= 2 && ev > 0 && ev < 16)
             std::fprintf(stderr, "[lra trace] %5llu %-12s arg %6lld  +%8.2f us\n", (unsigned long long)i, names[ev],
                          (long long)(tr[1 + 2 * i] & 0x00FFFFFFFFFFFFFFull), dt);
     }
     std::fprintf(stderr, "[lra trace] %llu events\n", (unsigned long long)n);
-    for (int e = 1; e < 14; ++e)
+    for (int e = 1; e < 16; ++e)
         if (cnt[e])
             std::fprintf(stderr, "[lra trace] %-12s n=%6lld total %9.1f us  mean %7.2f us\n", names[e],
                          (long long)cnt[e], tot[e], tot[e] / (double)cnt[e]);
