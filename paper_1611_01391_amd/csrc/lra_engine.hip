@@ -662,6 +662,48 @@ DI void unit_lower_inv_wave0(T* A, int k)
 }
 
 
+// The same inverse with each lane's column in registers (k <= KR <= 32),
+// both loops unrolled: per step one batch of broadcast LDS reads of the
+// multipliers (column t of L), then the updates; the same operations in the
+// same order as above.
+template <typename T, int KMAX, int LD, int KR>
+DI void unit_lower_inv_reg(T* A, int k)
+{
+    const int lane = threadIdx.x;
+    T x[KR];
+#pragma unroll
+    for (int r = 0; r < KR; ++r) x[r] = (T)(r == lane ? 1 : 0);
+#pragma unroll
+    for (int t = 0; t + 1 < KR; ++t) {
+        if (t + 1 < k) {
+            T l[KR];
+#pragma unroll
+            for (int s2 = t + 1; s2 < KR; ++s2) l[s2] = A[s2 * LD + t];
+#pragma unroll
+            for (int s2 = t + 1; s2 < KR; ++s2) x[s2] = x[s2] - l[s2] * x[t];
+        }
+    }
+    if (lane < k) {
+#pragma unroll
+        for (int r = 0; r < KR; ++r)
+            if (r < k) A[r * LD + KMAX + lane] = x[r];
+    }
+}
+
+template <typename T, int KMAX, int LD>
+DI void unit_lower_inv_solve(T* A, int k)
+{
+    constexpr int K16 = KMAX < 16 ? KMAX : 16, K32 = KMAX < 32 ? KMAX : 32;
+    if (k <= 8)
+        unit_lower_inv_reg<T, KMAX, LD, 8>(A, k);
+    else if (k <= K16)
+        unit_lower_inv_reg<T, KMAX, LD, K16>(A, k);
+    else if (k <= K32)
+        unit_lower_inv_reg<T, KMAX, LD, K32>(A, k);
+    else
+        unit_lower_inv_wave0<T, KMAX, LD>(A, k);
+}
+
 // A column of up to KR values of type LT held in registers, readable and
 // writable at a wavefront-uniform run-time row (lowered to register-indexed
 // moves; a vector of at most 32 dwords stays in registers, larger arrays
@@ -1200,7 +1242,7 @@ NOINL void basis_phase(const TaskDesc& td, Team& tio, int transpose, int started
         for (int e = threadIdx.x; e < keff * keff; e += NT)
             AUG[(e / keff) * LD + KMAX + e % keff] = (T)((e / keff) == (e % keff));
         __syncthreads();
-        if (threadIdx.x < 64) unit_lower_inv_wave0<T, KMAX, LD>(AUG, keff);
+        if (threadIdx.x < 64) unit_lower_inv_solve<T, KMAX, LD>(AUG, keff);
         __syncthreads();
         basis_product<T, KMAX>(rw, keff, AUG + KMAX, LD, 1);
     }
