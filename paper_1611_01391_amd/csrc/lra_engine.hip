@@ -1195,19 +1195,19 @@ NOINL int gepp_phase(const TaskDesc& td, Team& tio, int transpose, double thresh
             const T l = b[t * rw.ld] / piv;
             b[t * rw.ld] = l;
             for (int c0 = t + 1; c0 < k; c0 += 8) {
-                // columns past k repeat column c0: unconditional loads
                 T v[8], pv[8];
 #pragma unroll
-                for (int cc = 0; cc < 8; ++cc) {
-                    const int c = c0 + cc < k ? c0 + cc : c0;
-                    v[cc] = b[c * rw.ld];
-                    pv[cc] = sm.pay[c];
-                }
+                for (int cc = 0; cc < 8; ++cc)
+                    if (c0 + cc < k) {
+                        v[cc] = b[(c0 + cc) * rw.ld];
+                        pv[cc] = sm.pay[c0 + cc];
+                    }
 #pragma unroll
-                for (int cc = 0; cc < 8; ++cc) {
-                    v[cc] = v[cc] - l * pv[cc];
-                    if (c0 + cc < k) b[(c0 + cc) * rw.ld] = v[cc];
-                }
+                for (int cc = 0; cc < 8; ++cc)
+                    if (c0 + cc < k) {
+                        v[cc] = v[cc] - l * pv[cc];
+                        b[(c0 + cc) * rw.ld] = v[cc];
+                    }
                 if (c0 == t + 1) {
                     const double a = fabs((double)v[0]);
                     if (a > bv) { bv = a; br = r; }
@@ -1374,14 +1374,13 @@ NOINL int swap_phase(const TaskDesc& td, Team& tio, int transpose, int keff)
                 const T f = b[js * rw.ld];
                 const bool unit = (rw.r0 + r == is);
                 for (int c0 = 0; c0 < keff; c0 += CH) {
-                    // columns past keff repeat column c0: unconditional loads
                     T v[CH], gv[CH];
 #pragma unroll
-                    for (int cc = 0; cc < CH; ++cc) {
-                        const int c = c0 + cc < keff ? c0 + cc : c0;
-                        v[cc] = b[c * rw.ld];
-                        gv[cc] = sm.g[c];
-                    }
+                    for (int cc = 0; cc < CH; ++cc)
+                        if (c0 + cc < keff) {
+                            v[cc] = b[(c0 + cc) * rw.ld];
+                            gv[cc] = sm.g[c0 + cc];
+                        }
 #pragma unroll
                     for (int cc = 0; cc < CH; ++cc)
                         if (c0 + cc < keff) {
