@@ -185,11 +185,31 @@ def test_invdist_mixed(ctx):
     np.testing.assert_array_equal(Cg, exp)
 
 
+@pytest.mark.parametrize("team", [0, 4])
+@pytest.mark.parametrize("shape", [(2000, 1500, 40), (1500, 2000, 64)])
+def test_rank_above_32(ctx, team, shape):
+    """Ranks past 32 take the LDS forms of the small solves (warm start, L1
+    inverse, nucleus) and the general swap path (team 0: automatic size)."""
+    lra = _lra()
+    m, n, k = shape
+    _say(f"rank above 32 {shape} team {team}")
+    A, d = synth.rect_factor_gaussian(100 + k, m, n, k, 1e-6, k)
+    ref = oracle.ca_cur(oracle.dense(A), k, 2, 0.0, d.cand_cols, d.sample_rows, d.sample_cols)
+    kw = dict(init_cols=d.cand_cols, sample_rows=d.sample_rows, sample_cols=d.sample_cols)
+    if team:
+        kw["team_wgs"] = team
+    res = ctx.ca_cur(lra.dense(torch.from_numpy(A).cuda()), k, 2, 0.0, **kw)
+    assert _check_same(res, ref, GAMMA64, f"{shape} team {team}")
+    assert abs(res.err_est_rel - ref.err_est_rel) <= 1e-9 * ref.err_est_rel + 1e-15
+    np.testing.assert_allclose(res.U, ref.U, rtol=1e-8, atol=1e-8 * np.abs(ref.U).max())
+    np.testing.assert_array_equal(res.G, ref.G)
+
+
 # ---------------------------------------------------------------------------
 # maxvol alone
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("shape", [(300, 10), (5000, 32), (70000, 8)])
+@pytest.mark.parametrize("shape", [(300, 10), (5000, 32), (70000, 8), (4000, 48), (3000, 64)])
 def test_maxvol_alone(ctx, shape):
     _say(f"maxvol alone {shape}")
     m, k = shape
