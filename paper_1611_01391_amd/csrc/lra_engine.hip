@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lra_internal.h"
 
 namespace lra {
@@ -932,6 +934,19 @@ DI float keep(float v)
     return v;
 }
 
+// Runs body(width, c) over columns [c, end) in chunks of W, then one chunk
+// each of 8, 4, 2, 1 as needed: every load inside a chunk is unconditional
+// and no column is loaded twice (width is a std::integral_constant).
+template <int W, typename BODY>
+DI void column_chunks(int c, int end, BODY body)
+{
+    for (; c + W <= end; c += W) body(std::integral_constant<int, W>{}, c);
+    if (W > 8 && c + 8 <= end) { body(std::integral_constant<int, 8>{}, c); c += 8; }
+    if (c + 4 <= end) { body(std::integral_constant<int, 4>{}, c); c += 4; }
+    if (c + 2 <= end) { body(std::integral_constant<int, 2>{}, c); c += 2; }
+    if (c < end) body(std::integral_constant<int, 1>{}, c);
+}
+
 // ----------------------------------------------------------------------------
 // basis product on the matrix cores: slice <- slice(:, 0:kd) * W, W[d][c] at
 // W[d * wsd + c * wsc], d, c < kd.  Each wavefront owns 16-row tiles and
@@ -1194,25 +1209,24 @@ NOINL int gepp_phase(const TaskDesc& td, Team& tio, int transpose, double thresh
             T* b = rw.B + r;
             const T l = b[t * rw.ld] / piv;
             b[t * rw.ld] = l;
-            for (int c0 = t + 1; c0 < k; c0 += 8) {
-                T v[8], pv[8];
+            column_chunks<8>(t + 1, k, [&](auto w, int c0) {
+                constexpr int CW = decltype(w)::value;
+                T v[CW], pv[CW];
 #pragma unroll
-                for (int cc = 0; cc < 8; ++cc)
-                    if (c0 + cc < k) {
-                        v[cc] = b[(c0 + cc) * rw.ld];
-                        pv[cc] = sm.pay[c0 + cc];
-                    }
+                for (int cc = 0; cc < CW; ++cc) {
+                    v[cc] = b[(c0 + cc) * rw.ld];
+                    pv[cc] = sm.pay[c0 + cc];
+                }
 #pragma unroll
-                for (int cc = 0; cc < 8; ++cc)
-                    if (c0 + cc < k) {
-                        v[cc] = v[cc] - l * pv[cc];
-                        b[(c0 + cc) * rw.ld] = v[cc];
-                    }
+                for (int cc = 0; cc < CW; ++cc) {
+                    v[cc] = v[cc] - l * pv[cc];
+                    b[(c0 + cc) * rw.ld] = v[cc];
+                }
                 if (c0 == t + 1) {
                     const double a = fabs((double)v[0]);
                     if (a > bv) { bv = a; br = r; }
                 }
-            }
+            });
         }
         kl = bv >= 0.0 ? k2_make(bv, rw.r0 + br, 0) : k2_none();
         __syncthreads();
@@ -1373,24 +1387,23 @@ NOINL int swap_phase(const TaskDesc& td, Team& tio, int transpose, int keff)
                 T* b = rw.B + r;
                 const T f = b[js * rw.ld];
                 const bool unit = (rw.r0 + r == is);
-                for (int c0 = 0; c0 < keff; c0 += CH) {
-                    T v[CH], gv[CH];
+                column_chunks<CH>(0, keff, [&](auto w, int c0) {
+                    constexpr int CW = decltype(w)::value;
+                    T v[CW], gv[CW];
 #pragma unroll
-                    for (int cc = 0; cc < CH; ++cc)
-                        if (c0 + cc < keff) {
-                            v[cc] = b[(c0 + cc) * rw.ld];
-                            gv[cc] = sm.g[c0 + cc];
-                        }
+                    for (int cc = 0; cc < CW; ++cc) {
+                        v[cc] = b[(c0 + cc) * rw.ld];
+                        gv[cc] = sm.g[c0 + cc];
+                    }
 #pragma unroll
-                    for (int cc = 0; cc < CH; ++cc)
-                        if (c0 + cc < keff) {
-                            const int c = c0 + cc;
-                            const T nv = unit ? (T)(c == js ? 1 : 0) : v[cc] - f * gv[cc];
-                            b[c * rw.ld] = nv;
-                            const double a = fabs((double)nv);
-                            if (a > bv) { bv = a; br = r; bc = c; }
-                        }
-                }
+                    for (int cc = 0; cc < CW; ++cc) {
+                        const int c = c0 + cc;
+                        const T nv = unit ? (T)(c == js ? 1 : 0) : v[cc] - f * gv[cc];
+                        b[c * rw.ld] = nv;
+                        const double a = fabs((double)nv);
+                        if (a > bv) { bv = a; br = r; bc = c; }
+                    }
+                });
             }
         }
     }
