@@ -230,8 +230,8 @@ template <typename T, int KMAX>
 struct Smem {
     int64_t I[KMAX], J[KMAX], prevI[KMAX], prevJ[KMAX];
     double AUG[KMAX * 2 * KMAX];  // [M | right-hand sides], row stride 2 KMAX (T view for the strip)
-    double lucol[KMAX];           // register LU: the pivot column, one entry per lane
-    double lumul[KMAX];           // register LU: the multipliers of the current step
+    double lucol[NWAVE][KMAX];    // register LU, per wavefront: the pivot column
+    double lumul[NWAVE][KMAX];    // register LU, per wavefront: the step's multipliers
     double red[NT];           // fixed-order reductions
     double pts[KMAX];         // coordinates of the fixed index set (generated sources)
     T g[KMAX];                // swap update vector
@@ -775,8 +775,9 @@ struct RegCol<float, KR> {
     DI void dset(int i, float x) { v[i] = __float_as_uint(x); }
 };
 
-// The same solve with the matrix in registers, for k <= KR <= 32: lane c
-// holds column c (and c + 64 when NB = 2) of [M | R], rows 0..KR-1, loaded
+// The same solve with the matrix in registers, for k <= KR <= 32, on any one
+// wavefront (each has its own scratch): lane c holds column c (and c + 64
+// when NB = 2) of [M | R], rows 0..KR-1, loaded
 // once from A and the right-hand-side block stored back at the end, so the
 // elimination makes no LDS or global round trip per row.  Per step, lane t
 // passes its column through sm.lucol for the pivot search (lane s = row s)
@@ -785,12 +786,13 @@ struct RegCol<float, KR> {
 // (pos), which breaks ties exactly as the interchanging form does, and every
 // row sees the same operations in the same order, so the results are the
 // same bits.  pv (lane t) is the row chosen at step t; one pass puts the rows
-// in pivot order before the back substitution.
+// in pivot order before the back substitution.  Writes sm.ok and sm.minpiv;
+// wavefronts that solve with the same M at once write the same values.
 template <typename T, int KMAX, typename LT, int LD, int KR, int NB>
 DI void lu_reg_wave0(LT* A, int k, int rhs0, int nr, Smem<T, KMAX>& sm)
 {
     static_assert(KR <= KMAX && KR <= 32, "rows in registers");
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int W = k + nr;
     int lc[NB];
     bool act[NB];
@@ -808,8 +810,8 @@ DI void lu_reg_wave0(LT* A, int k, int rhs0, int nr, Smem<T, KMAX>& sm)
             const LT v = A[(r < k ? r : 0) * LD + lc[jb]];
             a[jb].set(r, (act[jb] && r < k) ? v : (LT)0);
         }
-    LT* cb = (LT*)sm.lucol;
-    LT* lb = (LT*)sm.lumul;
+    LT* cb = (LT*)sm.lucol[threadIdx.x >> 6];
+    LT* lb = (LT*)sm.lumul[threadIdx.x >> 6];
     double minpiv = INFINITY;
     int ok = 1;
     LT dreg = (LT)0;    // lane t: pivot of step t
@@ -1586,9 +1588,38 @@ DI void final_core(const TaskDesc& td, Team& tio)
         for (int a = 0; a < k; ++a) cg += fabs(Fm[a * LDF + threadIdx.x]);
     const double ng = k2_val(block_argmax(k2_make(cg, 0, 0), sm, tm));
     __syncthreads();
-    // U = G^{-1} and W = G^{-1} A[I,S] by one partial-pivot LU solve on
-    // wavefront 0, while the other wavefronts fetch A[Q,J] and A[Q,S]
-    if (threadIdx.x < 64) {
+    // U = G^{-1} and W = G^{-1} A[I,S] by partial-pivot LU solves.  k <= 32:
+    // three wavefronts each solve G against a third of the right-hand sides
+    // (I; the first and the last 32 columns of A[I,S]) with one column block
+    // per lane -- the same pivots, so the same bits as one solve -- while
+    // wavefront 3 fetches A[Q,J] and A[Q,S].  Larger k: one solve on
+    // wavefront 0, the fetches on the other three.
+    constexpr int K32 = KMAX < 32 ? KMAX : 32;
+    if (k <= K32 && s <= 64) {
+        const int wv = threadIdx.x >> 6;
+        if (wv == 0) {
+            lu_solve_wave0<T, KMAX, double, LDF, (2 * KMAX + 127) / 64, 1>(Fm, k, KMAX, k, sm);
+        } else if (wv == 1) {
+            lu_solve_wave0<T, KMAX, double, LDF, (2 * KMAX + 127) / 64, 1>(Fm, k, KMAX + k, s < 32 ? s : 32, sm);
+        } else if (wv == 2) {
+            if (s > 32) lu_solve_wave0<T, KMAX, double, LDF, (2 * KMAX + 127) / 64, 1>(Fm, k, KMAX + k + 32, s - 32, sm);
+        } else {
+            load_entries<double, 8>(
+                src, q * k, threadIdx.x - 192, 64,
+                [&](int e, int64_t& i, int64_t& j) {
+                    i = Qi[e / k];
+                    j = sm.J[e % k];
+                },
+                [&](int e, double v) { AQJ[e] = v; });
+            load_entries<double, 8>(
+                src, q * s, threadIdx.x - 192, 64,
+                [&](int e, int64_t& i, int64_t& j) {
+                    i = Qi[e / s];
+                    j = Si[e % s];
+                },
+                [&](int e, double v) { E[e] = v; });
+        }
+    } else if (threadIdx.x < 64) {
         lu_solve_wave0<T, KMAX, double, LDF, (2 * KMAX + 127) / 64, 2>(Fm, k, KMAX, k + s, sm);
     } else {
         load_entries<double, 8>(
