@@ -232,7 +232,7 @@ struct Smem {
     double AUG[KMAX * 2 * KMAX];  // [M | right-hand sides], row stride 2 KMAX (T view for the strip)
     double lucol[NWAVE][KMAX];    // register LU, per wavefront: the pivot column
     double lumul[NWAVE][KMAX];    // register LU, per wavefront: the step's multipliers
-    double red[NT];           // fixed-order reductions
+    double red[4 * NWAVE];    // fixed-order reductions: wavefront partials
     double pts[KMAX];         // coordinates of the fixed index set (generated sources)
     T g[KMAX];                // swap update vector
     T pay[KMAX];              // candidate / winning row
@@ -1521,19 +1521,29 @@ NOINL void write_factors(const TaskDesc& td, Smem<T, KMAX>& sm, const Team& tm)
     }
 }
 
-// Fixed-order block sum (every thread passes its partial; all get the total).
-template <typename T, int KMAX>
-DI double block_sum(double v, Smem<T, KMAX>& sm)
+// Fixed-order block sums of NV values (every thread passes its partials; all
+// get the totals): a butterfly inside each wavefront, then the wavefront
+// partials in order, with one workgroup barrier.
+template <int NV, typename T, int KMAX>
+DI void block_sums(double (&v)[NV], Smem<T, KMAX>& sm)
 {
-    sm.red[threadIdx.x] = v;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sm.red[i * NWAVE + wv] = v[i];
     __syncthreads();
-    for (int h = NT / 2; h >= 1; h >>= 1) {
-        if (threadIdx.x < h) sm.red[threadIdx.x] += sm.red[threadIdx.x + h];
-        __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double r = sm.red[i * NWAVE];
+#pragma unroll
+        for (int w = 1; w < NWAVE; ++w) r += sm.red[i * NWAVE + w];
+        v[i] = r;
     }
-    const double r = sm.red[0];
     __syncthreads();
-    return r;
 }
 
 // ----------------------------------------------------------------------------
@@ -1673,14 +1683,22 @@ DI void final_core(const TaskDesc& td, Team& tio)
         sa += av * av;
         sum += ev;
     }
-    se = block_sum(se, sm);
-    sa = block_sum(sa, sm);
-    sum = block_sum(sum, sm);
+    {
+        double r[3] = {se, sa, sum};
+        block_sums<3>(r, sm);
+        se = r[0];
+        sa = r[1];
+        sum = r[2];
+    }
     const double cnt = (double)q * (double)s;
     const double mean = sum / cnt;
     double vs = 0.0;
     for (int e = threadIdx.x; e < q * s; e += NT) vs += (E[e] - mean) * (E[e] - mean);
-    vs = block_sum(vs, sm);
+    {
+        double r[1] = {vs};
+        block_sums<1>(r, sm);
+        vs = r[0];
+    }
     if (threadIdx.x == 0) {
         const double ne = sqrt(se), na = sqrt(sa);
         sm.cond1 = ng * nu;
