@@ -1663,25 +1663,55 @@ DI void final_core(const TaskDesc& td, Team& tio)
     if (threadIdx.x < k)
         for (int a = 0; a < k; ++a) cu += fabs(Fm[a * LDF + KMAX + threadIdx.x]);
     const double nu = k2_val(block_argmax(k2_make(cu, 0, 0), sm, tm));
+    // E_QS = A[Q,S] - A[Q,J] W on the matrix cores: 16 x 16 output tiles
+    // spread over the wavefronts, k in steps of 4; loads at clamped indices,
+    // zero selected outside q, s and k
     double se = 0.0, sa = 0.0, sum = 0.0;
-    for (int e = threadIdx.x; e < q * s; e += NT) {
-        const int a = e / s, b = e % s;
-        const double* aq = AQJ + (int64_t)a * k;
-        double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-        int t = 0;
-        for (; t + 4 <= k; t += 4) {
-            c0 += aq[t] * W[t * LDF + b];
-            c1 += aq[t + 1] * W[(t + 1) * LDF + b];
-            c2 += aq[t + 2] * W[(t + 2) * LDF + b];
-            c3 += aq[t + 3] * W[(t + 3) * LDF + b];
+    {
+        constexpr int KB = KMAX / 4;
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int kbn = (k + 3) / 4;
+        const int ctn = (s + 15) / 16, ntiles = ((q + 15) / 16) * ctn;
+        for (int tile = wv; tile < ntiles; tile += NWAVE) {
+            const int r0 = (tile / ctn) * 16, c0 = (tile % ctn) * 16;
+            const int r = r0 + (lane & 15), c = c0 + (lane & 15);
+            const int rc = r < q ? r : 0, cc = c < s ? c : 0;
+            double av[KB], wv4[KB];
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                const int d = kb * 4 + (lane >> 4);
+                const int dc = d < k ? d : 0;
+                av[kb] = AQJ[rc * k + dc];
+                wv4[kb] = W[dc * LDF + cc];
+            }
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                av[kb] = keep(av[kb]);
+                wv4[kb] = keep(wv4[kb]);
+            }
+            d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                if (kb < kbn) {
+                    const int d = kb * 4 + (lane >> 4);
+                    const double x = (d < k && r < q) ? av[kb] : 0.0;
+                    const double y = (d < k && c < s) ? wv4[kb] : 0.0;
+                    acc = mfma16(x, y, acc);
+                }
+            }
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+                const int rr = r0 + Acc4<double>::row(lane, e4);
+                if (rr < q && c < s) {
+                    const double a0 = E[rr * s + c];
+                    const double ev = a0 - acc[e4];
+                    E[rr * s + c] = ev;
+                    se += ev * ev;
+                    sa += a0 * a0;
+                    sum += ev;
+                }
+            }
         }
-        for (; t < k; ++t) c0 += aq[t] * W[t * LDF + b];
-        const double av = E[e];
-        const double ev = av - ((c0 + c1) + (c2 + c3));
-        E[e] = ev;
-        se += ev * ev;
-        sa += av * av;
-        sum += ev;
     }
     {
         double r[3] = {se, sa, sum};
