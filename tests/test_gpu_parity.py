@@ -320,3 +320,29 @@ def test_global_strip_path_matches_lds_path(ctx):
         np.testing.assert_array_equal(r.U, ref.U)
         assert r.err_est_rel == ref.err_est_rel
     c2.close()
+
+
+# ---------------------------------------------------------------------------
+# nucleus and estimator on sample sizes off the 16 x 16 product tiles and on
+# both sides of the 32-column split of the nucleus solve
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("k,q,s", [(16, 37, 20), (32, 64, 48), (8, 50, 64), (32, 23, 31),
+                                   (32, 64, 33), (40, 45, 50), (1, 1, 1)])
+def test_nucleus_sample_shapes(ctx, k, q, s):
+    lra = _lra()
+    m, n = 900, 700
+    _say(f"nucleus sample shapes k {k} q {q} s {s}")
+    A, d = synth.rect_factor_gaussian(31 + k + q + s, m, n, k, 1e-6, k)
+    Q, S = synth.residual_sample(m, n, 500 + q + s, q, s)
+    assert len(Q) == q and len(S) == s
+    ref = oracle.ca_cur(oracle.dense(A), k, 2, 0.0, d.cand_cols, Q, S)
+    res = ctx.ca_cur(lra.dense(torch.from_numpy(A).cuda()), k, 2, 0.0, init_cols=d.cand_cols,
+                     sample_rows=Q, sample_cols=S)
+    torch.cuda.synchronize()
+    same = _check_same(res, ref, GAMMA64, f"k {k} q {q} s {s}")
+    assert abs(res.err_est_rel - ref.err_est_rel) <= 1e-10
+    if same:
+        assert abs(res.err_est_rel - ref.err_est_rel) <= 1e-9 * ref.err_est_rel + 1e-15
+        np.testing.assert_allclose(res.U, ref.U, rtol=1e-8, atol=1e-8 * np.abs(ref.U).max())
+        np.testing.assert_array_equal(res.G, ref.G)
