@@ -253,8 +253,8 @@ struct Team {
     int rank;
     uint32_t epoch;   // team barriers passed
     uint32_t xepoch;  // argmax exchanges done
-    bool failed;
-    int tog;  // LDS double-buffer selector of block_argmax
+    int32_t failed;   // 0 or 1 (a full word: the struct has no padding to copy)
+    int tog;          // LDS double-buffer selector of block_argmax
     uint32_t* err;
     int64_t timeout;
     uint64_t* trace;
