@@ -41,7 +41,8 @@ class Source(C.Structure):
 
 class Trace(C.Structure):
     _fields_ = [("min_pivot_gap", C.c_double), ("min_swap_gap", C.c_double),
-                ("min_stop_margin", C.c_double), ("min_rank_margin", C.c_double)]
+                ("min_stop_margin", C.c_double), ("min_rank_margin", C.c_double),
+                ("min_tol_margin", C.c_double)]
 
 
 class Options(C.Structure):
@@ -105,7 +106,7 @@ def _ptr(a: np.ndarray) -> int:
 
 def _new_trace() -> Trace:
     inf = float("inf")
-    return Trace(inf, inf, inf, inf)
+    return Trace(inf, inf, inf, inf, inf)
 
 
 # ---------------------------------------------------------------------------
@@ -243,7 +244,7 @@ class OracleResult:
     def min_gap(self) -> float:
         t = self.trace
         return min(t["min_pivot_gap"], t["min_swap_gap"], t["min_stop_margin"],
-                   t["min_rank_margin"])
+                   t["min_rank_margin"], t["min_tol_margin"])
 
 
 def ca_cur(src: HostSource, k: int, sweeps: int, tol: float, cand_cols, sample_rows,

@@ -203,6 +203,7 @@ int oracle_ca_cur(const oracle_source* src, int64_t m, int64_t n, int k, int swe
     memset(res, 0, sizeof(*res));
     res->trace.min_pivot_gap = res->trace.min_swap_gap = INFINITY;
     res->trace.min_stop_margin = res->trace.min_rank_margin = INFINITY;
+    res->trace.min_tol_margin = INFINITY;
     if (k < 1 || k > m || k > n || sweeps < 1 || opt->n_cand < k || opt->q < 1 || opt->s < 1 ||
         opt->tau < 0.0) {
         res->status = -1;

@@ -60,7 +60,9 @@ typedef struct {
     double min_pivot_gap;   /* partial-pivot LU: (|1st| - |2nd|) / |1st|   */
     double min_swap_gap;    /* swap argmax: (|1st| - |2nd|) / |1st|         */
     double min_stop_margin; /* | max|B| - (1+tau) | / (1+tau) at every test */
-    double min_rank_margin; /* | |pivot| - thresh | / thresh                */
+    double min_rank_margin; /* | |pivot| - thresh | / thresh, strip LU and
+                               warm-start elimination (fallback test)        */
+    double min_tol_margin;  /* | est_rel - tol | / tol at every rank level   */
 } oracle_trace;
 
 typedef struct {

@@ -71,6 +71,23 @@ def rect_factor_gaussian(seed: int, m: int, n: int, r: int, eps: float, k: int,
     return A, Draws(cand, Q, S)
 
 
+def spectrum_dense(seed: int, m: int, n: int, decay: float = 8.0, r: int = 160, n_cand: int = 80):
+    """A = U diag(sigma) V^T with orthonormal U (m x r), V (n x r) from the QR
+    factors of Gaussian matrices and sigma_j = 10^(-j / decay): a numerically
+    low-rank matrix whose error at rank k falls by a factor 10^(8 / decay) per
+    8 more columns, so that a tolerance between those levels makes the rank
+    grow by whole steps.  Draw order: the m x r Gaussian, the n x r Gaussian,
+    then the candidate columns choice(n, n_cand)."""
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    sig = 10.0 ** (-np.arange(r) / decay)
+    A = (U * sig[None, :]) @ V.T
+    cand = rng.choice(n, n_cand, replace=False).astype(np.int64)
+    Q, S = residual_sample(m, n, seed)
+    return np.ascontiguousarray(A), Draws(cand, Q, S)
+
+
 def dense_scaled(seed: int = 0, n: int = 16384, r: int = 32, k: int = 32, rel_noise: float = 1e-4,
                  chunk: int = 2048):
     """A = G1 G2 D + rel_noise (||G1 G2 D||_F / ||E||_F) E, cast to float32.

@@ -12,7 +12,10 @@ Coverage (every oracle function is pinned; none is "parity unpinned"):
                               the swap update); every single swap changes the
                               volume by |B_ic| (determinants); brute force
                               over all subsets (Hadamard bound, planted
-                              maximum, Cauchy closed form); bound (eqfuge).
+                              maximum, Cauchy closed form); bound (eqfuge);
+                              warm start falling back to the LU start on a
+                              singular or numerically singular C[I,:]
+                              equals the cold start.
 * oracle_nucleus           -- U G = I and G = A[I,J] against numpy.
 * oracle_residual          -- full sample equals the exact ||A - CUR||_F;
                               subsampled estimate within [0.5, 2] of it.
@@ -227,6 +230,60 @@ def test_maxvol_warm_fixed_point_and_cap():
         assert capped["capped"] and capped["swaps"] == 1
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_maxvol_warm_fallback_equals_cold_start(precision):
+    """A warm start whose C[I,:] is singular (two equal strip rows in I) or
+    numerically singular (rows equal up to far less than 64 u max|C|) fails the
+    rank test of its elimination, so the step restarts from the partial-pivot
+    LU of the whole strip: the result is exactly the cold start's.  The
+    decision's margin |pivot - thresh| / thresh is recorded."""
+    rng = np.random.default_rng(21)
+    m, k = 150, 6
+    C = rng.standard_normal((m, k))
+    C[40] = C[17]
+    u = 2.0 ** -53 if precision == "f64" else 2.0 ** -24
+    C[77] = C[23]
+    C[77, 2] += 1e-3 * u * np.abs(C).max()
+    if precision == "f32":
+        C = C.astype(np.float32).astype(np.float64)
+        C[77] = C[23]
+    cold = oracle.maxvol(C, tau=0.01, precision=precision)
+    for init in ([17, 40, 3, 5, 8, 9], [23, 1, 77, 5, 8, 9]):
+        warm = oracle.maxvol(C, tau=0.01, init=init, precision=precision)
+        np.testing.assert_array_equal(warm["I"], cold["I"])
+        np.testing.assert_array_equal(warm["B"], cold["B"])
+        assert warm["swaps"] == cold["swaps"] and warm["k_eff"] == k
+        assert warm["trace"].min_rank_margin <= 1.0
+    # a well-conditioned start passes the test with a wide margin and no restart
+    ok = oracle.maxvol(C, tau=0.01, init=cold["I"], precision=precision)
+    assert ok["swaps"] == 0 and ok["trace"].min_rank_margin > 1e3
+    np.testing.assert_array_equal(ok["I"], cold["I"])
+
+
+def test_warm_start_margin_reaches_the_driver_trace():
+    """In a whole run, warm starts happen from the second step on; their rank
+    tests feed the same margin as the first step's LU, so the driver's
+    min_rank_margin is the smaller of the two kinds."""
+    A, d = synth.plain_fp64(6)
+    cold_only = oracle.ca_cur(oracle.dense(A), 8, 1, 0.0, d.cand_cols, d.sample_rows, d.sample_cols,
+                              warm_start=False)
+    warm = oracle.ca_cur(oracle.dense(A), 8, 3, 0.0, d.cand_cols, d.sample_rows, d.sample_cols)
+    assert np.isfinite(warm.trace["min_rank_margin"])
+    assert warm.trace["min_rank_margin"] <= cold_only.trace["min_rank_margin"]
+
+
+def test_tol_margin_recorded():
+    """The stop-or-grow decision of each rank level compares est_rel with tol;
+    its margin |est_rel - tol| / tol is recorded (one level here)."""
+    A, d = synth.plain_fp64(3)
+    tol = 1e-6
+    r = oracle.ca_cur(oracle.dense(A), 8, 3, tol, d.cand_cols, d.sample_rows, d.sample_cols, k_max=16)
+    assert r.status == 0 and r.k == 8
+    assert r.trace["min_tol_margin"] == abs(r.err_est_rel - tol) / tol
+    r0 = oracle.ca_cur(oracle.dense(A), 8, 3, 0.0, d.cand_cols, d.sample_rows, d.sample_cols)
+    assert r0.trace["min_tol_margin"] == float("inf")
+
+
 # ---------------------------------------------------------------------------
 # nucleus and residual
 # ---------------------------------------------------------------------------
@@ -368,6 +425,29 @@ def test_adaptive_rank_cauchy():
     assert np.linalg.norm(E) / np.linalg.norm(A) <= 1e-9
     r8 = oracle.ca_cur(src, 8, 4, 0.0, cand, Q, S)
     assert r8.err_est_rel > 1e-10  # rank 8 alone is not enough
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_adaptive_rank_known_spectrum(seed):
+    """A = U diag(sigma) V^T with sigma_j = 10^(-j/8): the rank grows by whole
+    steps of 8 until the sampled error meets tol, and at every level the true
+    CUR error is bounded below by the Eckart-Young optimum, known here in
+    closed form from sigma (Lemma letrnc), and above by a small multiple."""
+    m, n = 3000, 2500
+    A, d = synth.spectrum_dense(seed, m, n, decay=8.0)
+    sig = 10.0 ** (-np.arange(160) / 8.0)
+    tol = 1e-3
+    r = oracle.ca_cur(oracle.dense(A), 8, 4, tol, d.cand_cols, d.sample_rows, d.sample_cols, k_max=40)
+    assert r.status == 0 and r.k == 32 and r.err_est_rel <= tol
+    for k in (8, 16, 24, 32):
+        rk = oracle.ca_cur(oracle.dense(A), k, 4, 0.0, d.cand_cols, d.sample_rows, d.sample_cols)
+        G = A[np.ix_(rk.I, rk.J)]
+        E = A - A[:, rk.J] @ np.linalg.solve(G, A[rk.I, :])
+        eps = np.linalg.norm(E) / np.linalg.norm(A)
+        eps_svd = math.sqrt((sig[k:] ** 2).sum() / (sig ** 2).sum())
+        assert eps_svd * (1 - 1e-6) <= eps <= 20 * eps_svd, (k, eps, eps_svd)
+        # a level below 32 misses tol, which is why the rank grew past it
+        assert (rk.err_est_rel > tol) == (k < 32), (k, rk.err_est_rel)
 
 
 def test_tol_not_met_at_cap():
