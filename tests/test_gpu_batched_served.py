@@ -76,10 +76,15 @@ def _clear(ref, gamma=GAMMA64):
 
 def _rank_decisions_clear(ref):
     """The oracle's rank decisions (LU pivots against 64 u max|strip|, the
-    estimate against tol at each level) are far from their thresholds: a GPU
-    run whose index sets differ by near-ties must still reach the same rank
-    and status."""
-    return ref.trace["min_rank_margin"] >= 1.0 and ref.trace["min_tol_margin"] >= 0.5
+    estimate against tol at each level) are far from their thresholds, and
+    the final generator is far from numerically singular
+    (1000 k cond1(G) u <= 1): a GPU run whose index sets differ by near-ties
+    must then still reach the same rank and status.  Without the second
+    condition the last pivot can itself be rounding noise (a block whose
+    sigma_k / sigma_1 is ~1e-15 has an LU pivot of a few hundred ulps on one
+    summation order and below 64 u on another), and both ranks are valid."""
+    return (ref.trace["min_rank_margin"] >= 1.0 and ref.trace["min_tol_margin"] >= 0.5
+            and 1000.0 * max(ref.k, 1) * ref.nucleus_cond1 * U64 <= 1.0)
 
 
 def _row_invariant(rows_fn, n, res, tau, u):
