@@ -92,6 +92,18 @@ def lib():
         L.oracle_ca_cur.argtypes = [C.POINTER(Source), C.c_int64, C.c_int64, C.c_int, C.c_int,
                                     C.c_double, C.c_int, C.POINTER(Options), P, P, P, P,
                                     C.POINTER(Result)]
+        L.oracle_cur_variant.restype = C.c_int
+        L.oracle_cur_variant.argtypes = [C.POINTER(Source), C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int,
+                                         C.c_int, C.c_int, C.c_int, C.POINTER(Options), P, P, P, P, P,
+                                         C.POINTER(Result)]
+        L.oracle_svd_jacobi.restype = C.c_int
+        L.oracle_svd_jacobi.argtypes = [P, C.c_int, P, P, P]
+        L.oracle_nucleus_trunc.restype = C.c_int
+        L.oracle_nucleus_trunc.argtypes = [C.POINTER(Source), P, P, C.c_int, C.c_int, P, P,
+                                           C.POINTER(C.c_double)]
+        L.oracle_residual_explicit.restype = None
+        L.oracle_residual_explicit.argtypes = [C.POINTER(Source), C.c_int64, C.c_int64, C.c_int, P, P, P,
+                                               P, C.c_int, P, C.c_int, P]
         L.oracle_splitmix64.restype = C.c_uint64
         L.oracle_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
         L.oracle_draw_distinct.restype = None
@@ -271,6 +283,73 @@ def ca_cur(src: HostSource, k: int, sweeps: int, tol: float, cand_cols, sample_r
                         G[:kk * kk].reshape(kk, kk).copy(), U[:kk * kk].reshape(kk, kk).copy(),
                         res.sweeps_done, res.swaps_total, res.entries_read, res.err_est_rel,
                         res.err_est_abs, res.err_mean, res.err_var, res.nucleus_cond1, tr)
+
+
+def cur_variant(src: HostSource, k: int, sweeps: int, cand_cols, sample_rows, sample_cols, init_rows=None,
+                cur_rank: int = 0, inner_sweeps: int = 4, nucleus_rank: int = 0, tau: float = 0.01,
+                max_swaps: int = 0, warm_start: bool = True, precision: str = "f64") -> OracleResult:
+    """The fixed-rank CUR algorithms of the C-A tests (see oracle.h):
+    sweeps = 0 takes I = init_rows, J = cand_cols[:k] at random; cur_rank
+    reduces the k x k generator to an r x r one of locally maximal volume
+    (Cynical); nucleus_rank truncates the nucleus (Primitive)."""
+    cand = np.ascontiguousarray(cand_cols, dtype=np.int64)
+    Q = np.ascontiguousarray(sample_rows, dtype=np.int64)
+    S = np.ascontiguousarray(sample_cols, dtype=np.int64)
+    rows = None if init_rows is None else np.ascontiguousarray(init_rows, dtype=np.int64)
+    opt = Options(float(tau), 0, 8, int(max_swaps), 1 if warm_start else 0,
+                  _ptr(cand), len(cand), _ptr(Q), len(Q), _ptr(S), len(S))
+    I = np.zeros(k, dtype=np.int64)
+    J = np.zeros(k, dtype=np.int64)
+    G = np.zeros(k * k)
+    U = np.zeros(k * k)
+    res = Result()
+    lib().oracle_cur_variant(C.byref(src.struct), src.m, src.n, int(k), int(sweeps), int(cur_rank),
+                             int(inner_sweeps), int(nucleus_rank), 0 if precision == "f64" else 1, C.byref(opt),
+                             None if rows is None else _ptr(rows), _ptr(I), _ptr(J), _ptr(G), _ptr(U),
+                             C.byref(res))
+    kk = max(res.k, 0)
+    tr = {f: getattr(res.trace, f) for f, _ in Trace._fields_}
+    return OracleResult(res.status, kk, I[:kk].copy(), J[:kk].copy(),
+                        G[:kk * kk].reshape(kk, kk).copy(), U[:kk * kk].reshape(kk, kk).copy(),
+                        res.sweeps_done, res.swaps_total, res.entries_read, res.err_est_rel,
+                        res.err_est_abs, res.err_mean, res.err_var, res.nucleus_cond1, tr)
+
+
+def svd_jacobi(G: np.ndarray):
+    """One-sided Jacobi SVD of a square matrix: (W, V, sv, sweeps) with
+    W = G V having orthogonal columns and sv their norms."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    k = G.shape[0]
+    W = np.zeros((k, k))
+    V = np.zeros((k, k))
+    sv = np.zeros(k)
+    sw = lib().oracle_svd_jacobi(_ptr(G), k, _ptr(W), _ptr(V), _ptr(sv))
+    return W, V, sv, sw
+
+
+def nucleus_trunc(src: HostSource, I, J, r: int):
+    """G = A[I,J] and its rank-r truncated pseudo-inverse."""
+    I = np.ascontiguousarray(I, dtype=np.int64)
+    J = np.ascontiguousarray(J, dtype=np.int64)
+    k = len(I)
+    G = np.zeros((k, k))
+    U = np.zeros((k, k))
+    cond = C.c_double(0.0)
+    rc = lib().oracle_nucleus_trunc(C.byref(src.struct), _ptr(I), _ptr(J), k, int(r), _ptr(G), _ptr(U),
+                                    C.byref(cond))
+    return rc, G, U, cond.value
+
+
+def residual_explicit(src: HostSource, I, J, U, Q, S):
+    I = np.ascontiguousarray(I, dtype=np.int64)
+    J = np.ascontiguousarray(J, dtype=np.int64)
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    Q = np.ascontiguousarray(Q, dtype=np.int64)
+    S = np.ascontiguousarray(S, dtype=np.int64)
+    out = np.zeros(6)
+    lib().oracle_residual_explicit(C.byref(src.struct), src.m, src.n, len(I), _ptr(I), _ptr(J), _ptr(U),
+                                   _ptr(Q), len(Q), _ptr(S), len(S), _ptr(out))
+    return dict(norm_e=out[0], norm_a=out[1], mean=out[2], var=out[3], est_abs=out[4], est_rel=out[5])
 
 
 def splitmix64(seed: int, ctr: int) -> int:

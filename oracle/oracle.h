@@ -133,6 +133,37 @@ int oracle_ca_cur(const oracle_source* src, int64_t m, int64_t n, int k, int swe
                   double tol, int precision, const oracle_options* opt,
                   int64_t* I, int64_t* J, double* G, double* U, oracle_result* res);
 
+/* The fixed-rank CUR algorithms that the C-A tests of Section 12.2 compare
+ * (tol is not used; every run is at fixed ranks):
+ *   sweeps >= 1: k x k generator from `sweeps` C-A sweeps at width k from
+ *     J0 = cand_cols[0..k) (Tests 2; sweeps = 1 with cur_rank: Tests 4);
+ *   sweeps == 0: I = init_rows[0..k), J = J0 at random (Tests 1, the random
+ *     p x q submatrix of Tests 3, the Primitive algorithm's random sets);
+ *   cur_rank in [1, k): Cynical reduction to an r x r submatrix of locally
+ *     maximal volume in the k x k generator, by up to inner_sweeps C-A
+ *     sweeps on that block (J0 = its first r columns); 0: none;
+ *   nucleus_rank in [1, k): nucleus U = (A[I,J])_r^+ (Primitive algorithm);
+ *     0 or k: U = A[I,J]^{-1}.
+ * The residual estimate as in oracle_ca_cur (explicit U when truncated).
+ * Returns the status (0 ok, 2 swap cap, 3 numerical rank, -2 singular
+ * generator or truncation, -6 non-finite entry, -1 invalid arguments). */
+int oracle_cur_variant(const oracle_source* src, int64_t m, int64_t n, int k, int sweeps, int cur_rank,
+                       int inner_sweeps, int nucleus_rank, int precision, const oracle_options* opt,
+                       const int64_t* init_rows, int64_t* I, int64_t* J, double* G, double* U,
+                       oracle_result* res);
+
+/* One-sided Jacobi SVD of the k x k row-major G: W = G V with orthogonal
+ * columns, V orthogonal, sv[j] = ||W[:,j]||.  Returns the sweeps taken. */
+int oracle_svd_jacobi(const double* G, int k, double* W, double* V, double* sv);
+/* G = A[I,J] and U = (G)_r^+ (rank-r truncated pseudo-inverse), k x k
+ * row-major; cond1 = ||G||_1 ||U||_1.  Returns 0, or -2 if sigma_r = 0. */
+int oracle_nucleus_trunc(const oracle_source* src, const int64_t* I, const int64_t* J, int k, int r,
+                         double* G, double* U, double* cond1);
+/* The sampled residual of oracle_residual with an explicit nucleus U. */
+void oracle_residual_explicit(const oracle_source* src, int64_t m, int64_t n, int k,
+                              const int64_t* I, const int64_t* J, const double* U,
+                              const int64_t* Q, int q, const int64_t* S, int s, double* out);
+
 /* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): the counter-based generator
  * used for default draws; value number `ctr` of stream `seed`. */
 uint64_t oracle_splitmix64(uint64_t seed, uint64_t ctr);
