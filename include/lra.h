@@ -56,7 +56,9 @@ typedef enum {
     LRA_ENOMEM = -3,        /* device allocation failed                               */
     LRA_EBUDGET = -4,       /* request exceeds the context's HBM budget               */
     LRA_EDEVICE = -5,       /* HIP runtime error or device-side time-out              */
-    LRA_ENONFINITE = -6     /* NaN or Inf met in a strip                              */
+    LRA_ENONFINITE = -6,    /* NaN or Inf met in a strip                              */
+    LRA_ESCRATCH = -7       /* lra_ca_cur_noalloc: the problem's workspace exceeds the
+                               fixed per-device scratch (LRA_NOALLOC_SCRATCH_BYTES)   */
 } lra_status;
 
 typedef enum { LRA_SRC_DENSE = 0, LRA_SRC_CAUCHY = 1, LRA_SRC_INVDIST = 2 } lra_src_kind;
@@ -169,6 +171,28 @@ void lra_destroy(lra_ctx* ctx);
  * LRA_EDEVICE. */
 lra_status lra_ca_cur(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k,
                       int sweeps, double tol, const lra_options* opts, lra_result* result);
+
+/* Allocation-free variant of lra_ca_cur, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, kernels and results as lra_ca_cur (bit for
+ * bit), but it calls no hipMalloc / hipHostMalloc / hipFree or other
+ * allocating device routine: the device workspace is a fixed array of
+ * LRA_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on
+ * until the process ends (its address is looked up once per device by
+ * lra_create), and the upload / read-back image is staged through a fixed
+ * host array of 1 MiB.  The context's hbm_budget_bytes does not apply.
+ * A problem whose workspace (control image, team control blocks, per-problem
+ * scratch, and a global strip of max(m, n) x max(k, k_max) elements when the
+ * strip rows do not fit the workgroups' LDS) exceeds the array is rejected
+ * with LRA_ESCRATCH before anything is launched.  The array keeps the last
+ * call's contents; every call clears the parts that must start at zero with
+ * a fill kernel.  Calls in one process are serialised by an internal lock
+ * (they share the array and the host staging; calls that overlapped on one
+ * GPU would race).  Errors: those of lra_ca_cur except LRA_ENOMEM and
+ * LRA_EBUDGET, plus LRA_ESCRATCH. */
+#define LRA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+lra_status lra_ca_cur_noalloc(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k,
+                              int sweeps, double tol, const lra_options* opts, lra_result* result);
 
 /* The maxvol sub-algorithm alone on a tall device strip (m x k, column-major,
  * leading dimension ld >= m, element type `dtype`): locally maximal-volume

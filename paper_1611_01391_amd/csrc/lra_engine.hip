@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "lra_internal.h"
@@ -2100,6 +2101,44 @@ hipError_t launch_zero(void* p, int64_t bytes, hipStream_t stream)
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, stream, (uint32_t*)p, words);
     return hipGetLastError();
+}
+
+// ----------------------------------------------------------------------------
+// fixed workspace of the allocation-free entry point (lra_ca_cur_noalloc)
+// ----------------------------------------------------------------------------
+//
+// Every device the library runs on holds one copy of this array until the
+// process ends.  On the host its name is only a stand-in for the symbol, not a
+// device address: host code never passes it to a kernel or a copy.  The device
+// address of each device's copy is looked up once, with that device current,
+// by noalloc_scratch_init (called from lra_create), and noalloc_scratch hands
+// it out afterwards.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_dev[NOALLOC_MAX_DEVICES];
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (scratch_dev[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    scratch_dev[device] = ptr;
+    return hipSuccess;
+}
+
+void* noalloc_scratch(int device)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    return scratch_dev[device];
 }
 
 }  // namespace lra

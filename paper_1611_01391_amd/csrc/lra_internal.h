@@ -119,4 +119,11 @@ inline int64_t team_ctl_bytes(int team_size)
     return CTL_HDR + 2ll * team_size * SLOT_STRIDE;
 }
 
+// Device workspace of the allocation-free entry point: a fixed array per
+// device (the upload image, team control blocks, per-problem scratch and any
+// global strip of one problem must fit in it).
+constexpr int64_t NOALLOC_SCRATCH_BYTES = 64ll << 20;
+// Host staging of that entry point (upload and read-back image).
+constexpr int64_t NOALLOC_HOST_BYTES = 1ll << 20;
+
 }  // namespace lra

@@ -13,6 +13,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,8 @@ const void* engine_kernel_ptr(int prec64, int kmax);
 hipError_t launch_engine(int prec64, int kmax, int grid, size_t smem, bool cooperative,
                          const EngineArgs& ea, hipStream_t stream);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t stream);
+hipError_t noalloc_scratch_init(int device);
+void* noalloc_scratch(int device);
 }  // namespace lra
 
 using namespace lra;
@@ -200,6 +203,7 @@ extern "C" const char* lra_status_str(lra_status s)
     case LRA_EBUDGET: return "exceeds the HBM budget";
     case LRA_EDEVICE: return "device error";
     case LRA_ENONFINITE: return "non-finite entry";
+    case LRA_ESCRATCH: return "workspace exceeds the fixed scratch of the allocation-free entry point";
     }
     return "unknown status";
 }
@@ -247,6 +251,10 @@ extern "C" lra_status lra_create(lra_ctx** out, void* stream, size_t budget)
                 return hip_fail(e, "hipFuncSetAttribute");
             }
         }
+    // device address of this device's copy of the allocation-free entry
+    // point's scratch array (once per device)
+    e = noalloc_scratch_init(c->device);
+    if (e != hipSuccess) { delete c; return hip_fail(e, "hipGetSymbolAddress(scratch)"); }
     LRA_LOG(1, "device %d: %d CUs, %d B LDS/block, wall clock %lld kHz", c->device, c->num_cu, c->max_lds,
             (long long)c->wall_rate_khz);
     *out = c;
@@ -811,8 +819,17 @@ static int severity(lra_status s)
 //   read back : states | I | J | error word, then G | U when asked for
 //   zeroed    : team control blocks, queue heads, trace
 //   scratch   : prevI, prevJ, final-phase work, global strips
+// Caller-provided buffers of a run (the allocation-free entry point): the
+// device workspace and the host staging, with their capacities.
+struct FixedBuffers {
+    uint8_t* dev;
+    int64_t dev_bytes;
+    uint8_t* host;
+    int64_t host_bytes;
+};
+
 static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, int phase_budget,
-                            lra_result* const* res)
+                            lra_result* const* res, const FixedBuffers* fixed = nullptr)
 {
     const size_t np = probs.size();
     if (np == 0) return LRA_OK;
@@ -865,12 +882,24 @@ static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, 
     }
     const int64_t total = L.size;
 
-    rs = ensure(ctx->dev, total, false, ctx);
-    if (rs != LRA_OK) return rs;
-    rs = ensure(ctx->host, u1, true, ctx);
-    if (rs != LRA_OK) return rs;
-    uint8_t* h = (uint8_t*)ctx->host.p;
-    uint8_t* d = (uint8_t*)ctx->dev.p;
+    uint8_t* h = nullptr;
+    uint8_t* d = nullptr;
+    if (fixed) {
+        if (total > fixed->dev_bytes || u1 > fixed->host_bytes) {
+            LRA_LOG(1, "workspace of %lld device bytes (%lld staged) exceeds the fixed scratch of %lld (%lld)",
+                    (long long)total, (long long)u1, (long long)fixed->dev_bytes, (long long)fixed->host_bytes);
+            return LRA_ESCRATCH;
+        }
+        d = fixed->dev;
+        h = fixed->host;
+    } else {
+        rs = ensure(ctx->dev, total, false, ctx);
+        if (rs != LRA_OK) return rs;
+        rs = ensure(ctx->host, u1, true, ctx);
+        if (rs != LRA_OK) return rs;
+        h = (uint8_t*)ctx->host.p;
+        d = (uint8_t*)ctx->dev.p;
+    }
 
     write_ctl(h, c, lp.pl);
     TaskDesc* htasks = (TaskDesc*)(h + c.tasks);
@@ -922,8 +951,8 @@ static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, 
 // public entry points
 // ----------------------------------------------------------------------------
 
-extern "C" lra_status lra_ca_cur(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k, int sweeps,
-                                 double tol, const lra_options* opts, lra_result* result)
+static lra_status ca_cur_one(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k, int sweeps,
+                             double tol, const lra_options* opts, lra_result* result, const FixedBuffers* fixed)
 {
     if (!ctx || !result) return LRA_EINVAL;
     lra_options o;
@@ -937,9 +966,34 @@ extern "C" lra_status lra_ca_cur(lra_ctx* ctx, const lra_source* src, int64_t m,
     probs[0].C_out = result->C_out;
     probs[0].R_out = result->R_out;
     lra_result* rp = result;
-    rs = run_batch(ctx, probs, prec64, 1 << 30, &rp);
+    rs = run_batch(ctx, probs, prec64, 1 << 30, &rp, fixed);
     if (rs != LRA_OK) return rs;
     return (lra_status)result->status;
+}
+
+extern "C" lra_status lra_ca_cur(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k, int sweeps,
+                                 double tol, const lra_options* opts, lra_result* result)
+{
+    return ca_cur_one(ctx, src, m, n, k, sweeps, tol, opts, result, nullptr);
+}
+
+// Host staging of the allocation-free entry point; the lock serialises its
+// calls (they share this array and the device's scratch array).
+namespace {
+std::mutex noalloc_mu;
+alignas(256) uint8_t noalloc_host[NOALLOC_HOST_BYTES];
+}  // namespace
+
+extern "C" lra_status lra_ca_cur_noalloc(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k,
+                                         int sweeps, double tol, const lra_options* opts, lra_result* result)
+{
+    static_assert(LRA_NOALLOC_SCRATCH_BYTES == (size_t)NOALLOC_SCRATCH_BYTES, "scratch size");
+    if (!ctx || !result) return LRA_EINVAL;
+    uint8_t* dev = (uint8_t*)noalloc_scratch(ctx->device);
+    if (!dev) return LRA_EDEVICE;  // lra_create looks the address up; never reached after it succeeded
+    std::lock_guard<std::mutex> lk(noalloc_mu);
+    const FixedBuffers fb{dev, NOALLOC_SCRATCH_BYTES, noalloc_host, NOALLOC_HOST_BYTES};
+    return ca_cur_one(ctx, src, m, n, k, sweeps, tol, opts, result, &fb);
 }
 
 extern "C" lra_status lra_maxvol(lra_ctx* ctx, const void* strip, int32_t dtype, int64_t m, int64_t ld, int k,

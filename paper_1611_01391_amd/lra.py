@@ -19,7 +19,9 @@ LIB_PATH = os.path.join(_HERE, "lib", "liblra.so")
 
 # status codes (lra_status)
 OK, TOL_NOT_MET, MAXVOL_CAP, NUMERICAL_RANK, PENDING = 0, 1, 2, 3, 4
-EINVAL, ERANK, ENOMEM, EBUDGET, EDEVICE, ENONFINITE = -1, -2, -3, -4, -5, -6
+EINVAL, ERANK, ENOMEM, EBUDGET, EDEVICE, ENONFINITE, ESCRATCH = -1, -2, -3, -4, -5, -6, -7
+# fixed device workspace of lra_ca_cur_noalloc (LRA_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 SRC_DENSE, SRC_CAUCHY, SRC_INVDIST = 0, 1, 2
 F32, F64 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
@@ -28,7 +30,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 EXPORTS = ["lra_default_options", "lra_create", "lra_destroy", "lra_ca_cur", "lra_maxvol",
            "lra_ca_cur_batched", "lra_submit", "lra_poll", "lra_wait", "lra_serve_config", "lra_set_timing",
            "lra_autotune_team", "lra_autotune_batched", "lra_tuning_save", "lra_tuning_load",
-           "lra_get_stats", "lra_status_str", "lra_version"]
+           "lra_get_stats", "lra_status_str", "lra_version", "lra_ca_cur_noalloc"]
 
 
 class LraError(RuntimeError):
@@ -99,6 +101,8 @@ def lib():
         L.lra_ca_cur.argtypes = [P, C.POINTER(Source), C.c_int64, C.c_int64, C.c_int, C.c_int,
                                  C.c_double, C.POINTER(Options), C.POINTER(ResultC)]
         L.lra_ca_cur.restype = C.c_int
+        L.lra_ca_cur_noalloc.argtypes = L.lra_ca_cur.argtypes
+        L.lra_ca_cur_noalloc.restype = C.c_int
         L.lra_maxvol.argtypes = [P, P, C.c_int32, C.c_int64, C.c_int64, C.c_int, C.c_double,
                                  C.c_int, P, P, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.lra_maxvol.restype = C.c_int
@@ -311,6 +315,20 @@ class Context:
     def ca_cur(self, src: DeviceSource, k: int, sweeps: int, tol: float = 0.0, *,
                init_cols=None, sample_rows=None, sample_cols=None, factors: bool = False,
                raise_on_error: bool = True, **opts) -> Result:
+        return self._ca_cur("lra_ca_cur", src, k, sweeps, tol, init_cols, sample_rows, sample_cols,
+                            factors, raise_on_error, opts)
+
+    def ca_cur_noalloc(self, src: DeviceSource, k: int, sweeps: int, tol: float = 0.0, *,
+                       init_cols=None, sample_rows=None, sample_cols=None, factors: bool = False,
+                       raise_on_error: bool = True, **opts) -> Result:
+        """lra_ca_cur_noalloc: as ca_cur, with the library's fixed per-device
+        workspace instead of allocated memory (the C_out / R_out tensors of
+        factors=True are the caller's, allocated here before the call)."""
+        return self._ca_cur("lra_ca_cur_noalloc", src, k, sweeps, tol, init_cols, sample_rows, sample_cols,
+                            factors, raise_on_error, opts)
+
+    def _ca_cur(self, fn, src, k, sweeps, tol, init_cols, sample_rows, sample_cols, factors, raise_on_error,
+                opts) -> Result:
         import torch
         o = default_options(**opts)
         cand, Q, S = _i64(init_cols), _i64(sample_rows), _i64(sample_cols)
@@ -333,10 +351,10 @@ class Context:
             R_t = torch.empty(kcap * src.n, dtype=dt, device=dev)
             buf.c.C_out = C_t.data_ptr()
             buf.c.R_out = R_t.data_ptr()
-        st = lib().lra_ca_cur(self._h, C.byref(src.struct), src.m, src.n, int(k), int(sweeps),
-                              float(tol), C.byref(o), C.byref(buf.c))
+        st = getattr(lib(), fn)(self._h, C.byref(src.struct), src.m, src.n, int(k), int(sweeps),
+                                float(tol), C.byref(o), C.byref(buf.c))
         if st < 0 and raise_on_error:
-            raise LraError(st, "lra_ca_cur")
+            raise LraError(st, fn)
         if st < 0:
             buf.c.status = st
         res = buf.to_result()

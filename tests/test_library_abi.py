@@ -48,3 +48,11 @@ def test_calls_reject_null_context():
     src = lra.Source()
     assert L.lra_ca_cur(None, C.byref(src), 10, 10, 2, 1, 0.0, None, C.byref(res)) == lra.EINVAL
     assert L.lra_ca_cur_batched(None, None, 1, None, None) == lra.EINVAL
+    assert L.lra_ca_cur_noalloc(None, C.byref(src), 10, 10, 2, 1, 0.0, None, C.byref(res)) == lra.EINVAL
+
+
+def test_noalloc_scratch_size_matches_header():
+    text = open(os.path.join(ROOT, "include", "lra.h")).read()
+    m = re.search(r"#define LRA_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == lra.NOALLOC_SCRATCH_BYTES
+    assert "fixed scratch" in lra.status_str(lra.ESCRATCH)
