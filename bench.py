@@ -1,27 +1,34 @@
 """Benchmarks of the C-A / CUR library on one MI355X.
 
-Default (the headline line): C-A / CUR of a dense 16384 x 16384 float32
-matrix.  A = G1 G2 D + 1e-4-scaled Gaussian noise (G1 16384x32, G2 32x16384,
-D log-uniform column scales in [0.1, 10]), stored float32 row-major in HBM;
-rank k = 32, 4 C-A sweeps from 32 seeded columns, maxvol tau = 0.01, 64 x 64
-sampled residual.  Only the gathered strips, the generator and the sample
-are read.  One step = one complete C-A / CUR (sweeps, nucleus, residual
-estimate) with the matrix resident.
+Default (no --workload): every leg of the metric in one run, one JSON line.
+The headline `value` is C-A / CUR of a dense 16384 x 16384 float32 matrix
+on the binary64 path: A = G1 G2 D + 1e-4-scaled Gaussian noise (G1
+16384x32, G2 32x16384, D log-uniform column scales in [0.1, 10]), stored
+float32 row-major in HBM; rank k = 32, 4 C-A sweeps from 32 seeded columns,
+maxvol tau = 0.01, 64 x 64 sampled residual.  Only the gathered strips, the
+generator and the sample are read.  One step = one complete C-A / CUR
+(sweeps, nucleus, residual estimate) with the matrix resident.  The other
+legs ride along as objects of the same line:
+  mixed_path        the same matrix on the binary32 path, parity against the
+                    binary32 oracle and error against the binary64 oracle
+  plain_512         dense binary64 512 x 512, W = G1 G2 + 1e-8 E, k = 8,
+                    3 sweeps
+  cauchy_2p20       implicit a_ij = 1/(s_i - t_j), m = n = 2^20, adaptive k
+                    8..40 to tol 1e-10
+  batched_vs_plain  every far-field block of a 1D adaptive tree over 2^20
+                    mixture points, kernel 1/|x - y|, adaptive k 8..48 to
+                    tol 1e-8: one batched launch vs one block per call
+  served_vs_plain   a stream of dense and Cauchy requests (m, n log-uniform
+                    in [1024, 65536], k in {8, 16, 32, 64} growing up to 64,
+                    tol log-uniform in [1e-10, 1e-4], binary32 or binary64):
+                    continuous batching vs sequential calls, throughput at
+                    saturation, p50 / p99 latency under Poisson arrivals
+Every leg carries its own oracle baseline: the CPU oracle as it stands,
+run on the host's cores (independent problems on a thread pool; the
+oracle's C calls release the interpreter lock).
 
-Other workloads (--workload):
-  plain      dense binary64 512 x 512, W = G1 G2 + 1e-8 E, k = 8, 3 sweeps
-  cauchy     implicit a_ij = 1/(s_i - t_j), m = n = 2^20, adaptive k 8..40 to
-             tol 1e-10 (binary64) or 1e-6 (--precision mixed)
-  multipole  every far-field block of a 1D adaptive tree over 2^20 mixture
-             points, kernel 1/|x - y|, adaptive k 8..48 to tol 1e-8, all
-             blocks in one batched launch vs one block per call
-  serve      a stream of dense and Cauchy requests (m, n log-uniform in
-             [1024, 65536], k in {8, 16, 32, 64}, tol log-uniform in
-             [1e-10, 1e-4], binary32 or binary64): served (continuous
-             batching) vs plain sequential calls, throughput at saturation
-             and p50 / p99 latency under Poisson arrivals
-
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+--workload X runs one leg alone with its own line.  --gpus N > 1 is
+refused: this build runs on one GPU.
 """
 from __future__ import annotations
 
@@ -64,9 +71,23 @@ def host_info():
     return {"nproc": os.cpu_count(), "cpu": model}
 
 
-def _profiled_traffic(summary, kernel_src="paper_1611_01391_amd/csrc/lra_engine.hip"):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, or
-    None when the engine source has changed since the counters were taken."""
+def host_threads(args):
+    """Threads for the oracle baselines: --threads, else the host's cores
+    (at most 16, the CPU share of one GPU on the box)."""
+    return max(1, args.threads or min(16, os.cpu_count() or 1))
+
+
+def pool_map(fn, items, threads):
+    """fn over items on a thread pool (the oracle's ctypes calls release the
+    interpreter lock, so independent problems run on separate cores)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(fn, items))
+
+
+def _profiled(summary, key, kernel_src="paper_1611_01391_amd/csrc/lra_engine.hip"):
+    """A figure from a committed rocprofv3 summary, or None when the engine
+    source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", summary)
     try:
@@ -74,11 +95,11 @@ def _profiled_traffic(summary, kernel_src="paper_1611_01391_amd/csrc/lra_engine.
         sha = hashlib.sha256(open(os.path.join(ROOT, kernel_src), "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    vals = dict(l.split(":", 1) for l in text.splitlines()
-                if l.startswith(("traffic_bytes_per_launch:", "engine_source_sha256_prefix:")))
+    vals = dict(l.split(":", 1) for l in text.splitlines() if ":" in l and not l.startswith((" ", "#", "|")))
     if vals.get("engine_source_sha256_prefix", "").strip() != sha:
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    v = vals.get(key)
+    return float(v) if v is not None else None
 
 
 def _median_time(fn, reps):
@@ -89,6 +110,21 @@ def _median_time(fn, reps):
         out = fn()
         ts.append(time.perf_counter() - t0)
     return float(np.median(ts)), out
+
+
+def _cpu_throughput(fn, runs, threads, unit, what):
+    """The oracle run `runs` times on `threads` threads: throughput over the
+    wall clock, with the single-thread median of the first runs beside it."""
+    t1 = time.perf_counter()
+    _, ref = _median_time(fn, 1)
+    single = time.perf_counter() - t1
+    t0 = time.perf_counter()
+    pool_map(lambda _: fn(), range(runs), threads)
+    wall = time.perf_counter() - t0
+    return {"value": runs / wall, "unit": unit, "cores": threads, "kind": "oracle",
+            "sample": f"{runs} independent runs of {what} on {threads} host threads in {wall:.2f}s "
+                      f"(one run alone: {single:.3f}s)",
+            "single_thread_value": 1.0 / single, "host": host_info()}, ref
 
 
 def _timed_steps(ctx, torch, fn, steps, warmup):
@@ -126,6 +162,20 @@ def _dense_alg_bytes(m, n, k, sweeps, q, s, esz):
     return entries * esz
 
 
+_DENSE_CACHE = {}
+
+
+def _dense_input(args):
+    key = (args.seed, args.n, args.k)
+    if key not in _DENSE_CACHE:
+        import synth
+        t0 = time.time()
+        _DENSE_CACHE.clear()
+        _DENSE_CACHE[key] = synth.dense_scaled(args.seed, n=args.n, r=32, k=args.k)
+        log(f"# generated {args.n}x{args.n} float32 input in {time.time() - t0:.1f}s")
+    return _DENSE_CACHE[key]
+
+
 def bench_dense(args, plain=False):
     import torch
 
@@ -140,9 +190,7 @@ def bench_dense(args, plain=False):
         desc = "dense binary64 512x512 (W = G1 G2 + 1e-8 E, rank 8), k=8, 3 C-A sweeps, 64x64 residual sample"
     else:
         n, k, sweeps = args.n, args.k, args.sweeps
-        t0 = time.time()
-        A, d = synth.dense_scaled(args.seed, n=n, r=32, k=k)
-        log(f"# generated {n}x{n} float32 input in {time.time() - t0:.1f}s")
+        A, d = _dense_input(args)
         esz = 4
         prec = lra.PREC_FP64 if args.precision == "fp64" else lra.PREC_MIXED
         desc = (f"dense float32 {n}x{n} (rank-32 scaled factor-Gaussian + 1e-4 noise), k={k}, "
@@ -180,28 +228,40 @@ def bench_dense(args, plain=False):
     if not args.no_cpu_baseline:
         import oracle
         osrc = oracle.dense(A)
-        reps = max(1, args.cpu_samples)
-        med, ref = _median_time(lambda: oracle.ca_cur(osrc, k, sweeps, 0.0, d.cand_cols, d.sample_rows,
-                                                      d.sample_cols,
-                                                      precision="f64" if prec == lra.PREC_FP64 else "f32"),
-                                reps)
-        cpu = {"value": 1.0 / med, "unit": "CUR LRAs/s", "cores": 1, "kind": "oracle",
-               "sample": f"{reps} full C-A/CUR runs of the same {n}x{n} workload, single-threaded, "
-                         f"median {med:.3f}s", "host": host_info()}
-        parity = {"oracle_status": int(ref.status), "same_I": bool(np.array_equal(ref.I, res.I)),
-                  "same_J": bool(np.array_equal(ref.J, res.J)),
+        oprec = "f64" if prec == lra.PREC_FP64 else "f32"
+        threads = host_threads(args)
+        runs = max(2 * threads, args.cpu_samples) if not plain else 1000 * threads
+        cpu, ref = _cpu_throughput(
+            lambda: oracle.ca_cur(osrc, k, sweeps, 0.0, d.cand_cols, d.sample_rows, d.sample_cols, precision=oprec),
+            runs, threads, "CUR LRAs/s", f"the full C-A/CUR of the same {n}x{n} workload")
+        parity = {"oracle_precision": oprec, "oracle_status": int(ref.status),
+                  "same_I": bool(np.array_equal(ref.I, res.I)), "same_J": bool(np.array_equal(ref.J, res.J)),
                   "est_rel_gpu": res.err_est_rel, "est_rel_oracle": ref.err_est_rel,
                   "oracle_min_gap": ref.min_gap()}
+        if oprec == "f32":
+            # the binary32 path's error against the binary64 oracle's
+            ref64 = oracle.ca_cur(osrc, k, sweeps, 0.0, d.cand_cols, d.sample_rows, d.sample_cols)
+            parity["est_rel_oracle_f64"] = ref64.err_est_rel
+            parity["est_rel_ratio_vs_f64"] = res.err_est_rel / ref64.err_est_rel if ref64.err_est_rel else None
+            parity["same_I_as_f64"] = bool(np.array_equal(ref64.I, res.I))
+            parity["same_J_as_f64"] = bool(np.array_equal(ref64.J, res.J))
     out = _base(args, args.steps / el, "CUR LRAs/s", ms_per_step,
                 "f64" if prec == lra.PREC_FP64 else "f32",
                 {"workload": desc, "m": n, "n": n, "k": k, "sweeps": sweeps,
                  "precision": "fp64" if prec == lra.PREC_FP64 else "mixed", "autotuned": tuned})
     traffic = None
     if not plain and (n, k, sweeps, args.precision) == (16384, 32, 4, "fp64"):
-        traffic = _profiled_traffic("engine_kernel_dense16384_k32.md")
-    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "engine_kernel",
-                       "kernel_ms": kernel_ms, "algorithmic_bytes": alg_bytes}
+        traffic = _profiled("engine_kernel_dense16384_k32.md", "traffic_bytes_per_launch")
+    if plain:
+        # one workgroup, all in LDS: a latency-bound launch (no roofline binds)
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "engine_kernel",
+                           "kernel_ms": kernel_ms, "algorithmic_bytes": alg_bytes,
+                           "note": "latency-bound: one workgroup, the strips live in LDS"}
+    else:
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "engine_kernel",
+                           "kernel_ms": kernel_ms, "algorithmic_bytes": alg_bytes}
     if traffic:
         out["roofline"]["traffic_GBps"] = traffic / (kernel_ms * 1e-3) / 1e9
     out["cpu_baseline"] = cpu
@@ -209,6 +269,7 @@ def bench_dense(args, plain=False):
     out["result"] = {"status": int(res.status), "k": int(res.k), "swaps": int(res.swaps_total),
                      "est_rel": res.err_est_rel, "entries_read": int(res.entries_read)}
     ctx.close()
+    del At
     return out
 
 
@@ -246,13 +307,12 @@ def bench_cauchy(args):
     if not args.no_cpu_baseline:
         import oracle
         osrc = oracle.cauchy(s, t)
-        reps = max(1, min(args.cpu_samples, 5))
-        med, ref = _median_time(lambda: oracle.ca_cur(osrc, 8, 4, tol, d.cand_cols, d.sample_rows, d.sample_cols,
-                                                      k_max=40, precision="f64" if f64 else "f32"), reps)
-        cpu = {"value": 1.0 / med, "unit": "CUR LRAs/s", "cores": 1, "kind": "oracle",
-               "sample": f"{reps} full adaptive C-A/CUR runs of the same 2^20 x 2^20 Cauchy workload, "
-                         f"single-threaded, median {med:.3f}s (oracle status {ref.status}, k {ref.k}, "
-                         f"est {ref.err_est_rel:.3e})", "host": host_info()}
+        threads = host_threads(args)
+        cpu, ref = _cpu_throughput(
+            lambda: oracle.ca_cur(osrc, 8, 4, tol, d.cand_cols, d.sample_rows, d.sample_cols, k_max=40,
+                                  precision="f64" if f64 else "f32"),
+            threads, threads, "CUR LRAs/s", "the full adaptive C-A/CUR of the same 2^20 x 2^20 Cauchy workload")
+        cpu["oracle_result"] = {"status": int(ref.status), "k": int(ref.k), "est_rel": ref.err_est_rel}
     out = _base(args, args.steps / el, "CUR LRAs/s", el * 1e3 / args.steps, "f64" if f64 else "f32",
                 {"workload": f"implicit Cauchy 1/(s_i - t_j), s ~ U[0,1], t ~ U[2,3], m = n = 2^20, adaptive k "
                              f"8..40 step 8, tol {tol:g}, up to 4 sweeps per rank",
@@ -277,14 +337,12 @@ def bench_multipole(args):
     from paper_1611_01391_amd import lra
 
     N = args.points
-    tol, kmax = 1e-8, 48
+    tol, kmax = args.mp_tol, 48
     f64 = args.precision == "fp64"
     t0 = time.time()
     x, blocks, dense_blocks = synth.multipole(args.seed, N, 4096, 96)
     log(f"# {len(blocks)} far-field blocks ({len(dense_blocks)} left dense) in {time.time() - t0:.1f}s")
     xd = torch.from_numpy(x if f64 else x.astype(np.float32)).cuda()
-    if not f64:
-        tol = 1e-5
     prec = lra.PREC_FP64 if f64 else lra.PREC_MIXED
     jobs = [(lra.invdist(xd[a0:a1], xd[b0:b1]), 8, 4, tol) for (a0, a1, b0, b1) in blocks]
     ctx = lra.Context()
@@ -326,10 +384,10 @@ def bench_multipole(args):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        step = max(1, len(blocks) // 128)
-        sample = list(range(0, len(blocks), step))
-        c0 = time.perf_counter()
-        for b in sample:
+        threads = host_threads(args)
+        xo = x if f64 else x.astype(np.float32)
+
+        def one(b):
             a0, a1, b0, b1 = blocks[b]
             m, n = a1 - a0, b1 - b0
             kc = max(8, min(kmax, m, n))
@@ -337,14 +395,17 @@ def bench_multipole(args):
             cand = oracle.draw_distinct(sd, n, min(n, 2 * kc))
             Q = np.sort(oracle.draw_distinct(sd + 1, m, min(64, m)))
             S = np.sort(oracle.draw_distinct(sd + 2, n, min(64, n)))
-            oracle.ca_cur(oracle.invdist(x[a0:a1], x[b0:b1]), 8, 4, tol, cand, Q, S, k_max=kmax,
-                          precision="f64" if f64 else "f32")
+            r = oracle.ca_cur(oracle.invdist(xo[a0:a1], xo[b0:b1]), 8, 4, tol, cand, Q, S, k_max=kmax,
+                              precision="f64" if f64 else "f32")
+            return r.status >= 0 and r.err_est_rel <= tol
+        # every block, largest first (dynamic assignment to the threads)
+        order = sorted(range(len(blocks)), key=lambda b: -((blocks[b][1] - blocks[b][0]) + (blocks[b][3] - blocks[b][2])))
+        c0 = time.perf_counter()
+        met_cpu = sum(pool_map(one, order, threads))
         cs = time.perf_counter() - c0
-        frac = sum((blocks[b][1] - blocks[b][0]) + (blocks[b][3] - blocks[b][2]) for b in sample) / \
-            sum((b[1] - b[0]) + (b[3] - b[2]) for b in blocks)
-        cpu = {"value": len(sample) / cs, "unit": "CUR LRAs/s (blocks/s)", "cores": 1, "kind": "oracle",
-               "sample": f"every {step}th block ({len(sample)} blocks, {frac:.1%} of the rows+columns), "
-                         f"single-threaded, {cs:.2f}s", "host": host_info()}
+        cpu = {"value": len(blocks) / cs, "unit": "CUR LRAs/s (blocks/s)", "cores": threads, "kind": "oracle",
+               "sample": f"all {len(blocks)} blocks of the same pass, largest first on {threads} host threads, "
+                         f"{cs:.2f}s; {met_cpu} meet tol", "host": host_info()}
     out = _base(args, len(blocks) / batched_s, "CUR LRAs/s (blocks/s)", batched_s * 1e3, "f64" if f64 else "f32",
                 {"workload": f"1D multipole far field: N = {N} mixture points, adaptive binary tree (leaves <= 4096), "
                              f"{len(blocks)} admissible blocks (dist >= width, min side 96), kernel 1/|x-y|, "
@@ -353,9 +414,11 @@ def bench_multipole(args):
                  "autotuned": tuned})
     out["roofline"] = _alu_roofline(entries, kernel_ms)
     out["cpu_baseline"] = cpu
+    met_plain = sum(1 for r in out_p if r.status >= 0 and r.err_est_rel <= tol)
     out["batched_vs_plain"] = {"batched_blocks_per_s": len(blocks) / batched_s,
                                "plain_blocks_per_s": len(blocks) / plain_s,
                                "speedup": plain_s / batched_s, "identical_results": same,
+                               "tol_met_batched": met, "tol_met_plain": met_plain,
                                "blocks": len(blocks)}
     out["result"] = {"statuses": statuses, "k_hist": ks, "tol_met": met, "entries_read": int(entries)}
     ctx.close()
@@ -424,7 +487,8 @@ def bench_serve(args):
 
     def kw(i):
         sp = specs[i]
-        return dict(precision=lra.PREC_FP64 if sp.dtype == "f64" else lra.PREC_MIXED, seed=i)
+        return dict(precision=lra.PREC_FP64 if sp.dtype == "f64" else lra.PREC_MIXED, seed=i,
+                    k_max=min(args.serve_kmax, sp.m, sp.n))
 
     ctx = lra.Context()
     # plain: sequential blocking calls
@@ -489,36 +553,60 @@ def bench_serve(args):
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        sample = [i for i, s in enumerate(specs) if s.kind == "cauchy"][:20]
-        c0 = time.perf_counter()
-        for i in sample:
+        threads = host_threads(args)
+        cau = [i for i, sp in enumerate(specs) if sp.kind == "cauchy"][:40]
+        den = [i for i, sp in enumerate(specs) if sp.kind == "dense" and sp.m * sp.n <= (1 << 24)][:40]
+        hosts = {}
+        for i in den:
+            # host copy of the request's window of its pool matrix
             sp = specs[i]
-            rng = np.random.default_rng(args.seed * 100003 + i)
-            dt = np.float64 if sp.dtype == "f64" else np.float32
-            sx = rng.uniform(0, 1, sp.m).astype(dt)
-            tx = rng.uniform(2, 3, sp.n).astype(dt)
-            kc = sp.k
-            sd = i
-            cand = oracle.draw_distinct(sd, sp.n, min(sp.n, 2 * kc))
-            Q = np.sort(oracle.draw_distinct(sd + 1, sp.m, min(64, sp.m)))
-            S = np.sort(oracle.draw_distinct(sd + 2, sp.n, min(64, sp.n)))
-            oracle.ca_cur(oracle.cauchy(sx, tx), sp.k, sweeps, sp.tol, cand, Q, S,
-                          precision=sp.dtype)
+            hosts[i] = pool[(sp.k, sp.dtype)][:sp.m, :sp.n].cpu().numpy()
+
+        def one(i):
+            sp = specs[i]
+            if sp.kind == "dense":
+                osrc = oracle.dense(hosts[i])
+            else:
+                rng = np.random.default_rng(args.seed * 100003 + i)
+                dt = np.float64 if sp.dtype == "f64" else np.float32
+                osrc = oracle.cauchy(rng.uniform(0, 1, sp.m).astype(dt), rng.uniform(2, 3, sp.n).astype(dt))
+            km = min(args.serve_kmax, sp.m, sp.n)
+            kc = max(sp.k, km)
+            cand = oracle.draw_distinct(i, sp.n, min(sp.n, 2 * kc))
+            Q = np.sort(oracle.draw_distinct(i + 1, sp.m, min(64, sp.m)))
+            S = np.sort(oracle.draw_distinct(i + 2, sp.n, min(64, sp.n)))
+            r = oracle.ca_cur(osrc, sp.k, sweeps, sp.tol, cand, Q, S, k_max=km, precision=sp.dtype)
+            return r.status >= 0 and r.err_est_rel <= sp.tol
+        sample = cau + den
+        c0 = time.perf_counter()
+        met_cpu = sum(pool_map(one, sample, threads))
         cs = time.perf_counter() - c0
-        cpu = {"value": len(sample) / cs, "unit": "requests/s", "cores": 1, "kind": "oracle",
-               "sample": f"the first {len(sample)} Cauchy requests of the stream, single-threaded, {cs:.2f}s "
-                         f"(dense requests need host copies of the pool and are not sampled)",
-               "host": host_info()}
+        del hosts
+        cpu = {"value": len(sample) / cs, "unit": "requests/s", "cores": threads, "kind": "oracle",
+               "sample": f"the first {len(cau)} Cauchy requests and the first {len(den)} dense requests with "
+                         f"m n <= 2^24 (host copies of their pool windows) on {threads} host threads, "
+                         f"{cs:.2f}s; {met_cpu} meet tol", "host": host_info()}
+    dense_bytes = sum(r.entries_read * (8 if sp.dtype == "f64" else 4)
+                      for r, sp in zip(served, specs) if sp.kind == "dense" and r.status >= 0)
+    met_plain = sum(1 for r, sp in zip(plain, specs) if r.status >= 0 and r.err_est_rel <= sp.tol)
+    met_served = sum(1 for r, sp in zip(served, specs) if r.status >= 0 and r.err_est_rel <= sp.tol)
     out = _base(args, thr_served, "requests/s (CUR LRAs/s)", served_s * 1e3 / count, "f64+f32",
                 {"workload": f"served stream of {count} requests (dense pool windows and Cauchy kernels, m, n "
                              f"log-uniform [1024, {args.max_dim}], k in {{8,16,32,64}}, tol log-uniform "
-                             f"[1e-10, 1e-4], binary32/binary64, up to 4 sweeps), continuous batching",
-                 "requests": count, "max_dim": args.max_dim, "phases_per_tick": args.phases})
+                             f"[1e-10, 1e-4], rank growth up to {args.serve_kmax}, binary32/binary64, up to 4 sweeps per "
+                             f"rank), continuous batching",
+                 "requests": count, "k_max": args.serve_kmax, "max_dim": args.max_dim, "phases_per_tick": args.phases})
     out["steps"] = 1
-    out["roofline"] = None
+    ach = dense_bytes / served_s / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "engine_kernel_all",
+                       "algorithmic_bytes": dense_bytes,
+                       "note": "entries read by the dense requests over the served makespan (the Cauchy "
+                               "requests generate theirs)"}
     out["cpu_baseline"] = cpu
     out["served_vs_plain"] = {"served_requests_per_s": thr_served, "plain_requests_per_s": thr_plain,
                               "speedup": thr_served / thr_plain, "identical_results": same,
+                              "tol_met_plain": met_plain, "tol_met_served": met_served,
                               "offered_load_per_s": lam,
                               "latency_ms": {"plain_p50": lp[0], "plain_p99": lp[1],
                                              "served_p50": ls[0], "served_p99": ls[1]},
@@ -530,24 +618,72 @@ def bench_serve(args):
     return out
 
 
+def _leg(name, fn, args, **over):
+    """Run one leg with its own step counts; returns its line and wall time."""
+    import copy
+    a = copy.copy(args)
+    for key, val in over.items():
+        setattr(a, key, val)
+    t0 = time.time()
+    out = fn(a)
+    wall = time.time() - t0
+    log(f"# leg {name}: {wall:.1f}s")
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+    out["wall_s"] = wall
+    return out
+
+
+def _summary(leg, keys):
+    return {key: leg.get(key) for key in keys if key in leg}
+
+
+def bench_all(args):
+    """The headline dense leg, with every other leg of the metric attached."""
+    t0 = time.time()
+    out = _leg("dense fp64", bench_dense, args)
+    keep = ("value", "unit", "ms_per_step", "steps", "warmup", "dtype", "config", "roofline", "cpu_baseline",
+            "parity", "result", "wall_s")
+    mixed = _leg("dense mixed", bench_dense, args, precision="mixed", steps=10, warmup=2)
+    out["mixed_path"] = _summary(mixed, keep)
+    plain = _leg("plain 512", lambda a: bench_dense(a, plain=True), args, steps=50, warmup=5)
+    out["plain_512"] = _summary(plain, keep)
+    cau = _leg("cauchy 2^20", bench_cauchy, args, steps=10, warmup=2)
+    out["cauchy_2p20"] = _summary(cau, keep)
+    mp = _leg("multipole", bench_multipole, args, steps=3, warmup=1)
+    out["batched_vs_plain"] = dict(mp["batched_vs_plain"], config=mp["config"], roofline=mp["roofline"],
+                                   cpu_baseline=mp["cpu_baseline"], result=mp["result"], wall_s=mp["wall_s"],
+                                   kernel_ms=mp["roofline"]["kernel_ms"])
+    sv = _leg("serve", bench_serve, args)
+    out["served_vs_plain"] = dict(sv["served_vs_plain"], config=sv["config"], roofline=sv["roofline"],
+                                  cpu_baseline=sv["cpu_baseline"], result=sv["result"], wall_s=sv["wall_s"])
+    out["wall_s_total"] = time.time() - t0
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["dense", "plain", "cauchy", "multipole", "serve"], default="dense")
+    ap.add_argument("--workload", choices=["all", "dense", "plain", "cauchy", "multipole", "serve"], default="all")
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--sweeps", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--points", type=int, default=1 << 20, help="multipole: number of points")
+    ap.add_argument("--mp-tol", type=float, default=1e-8, help="multipole: tolerance")
     ap.add_argument("--requests", type=int, default=1000, help="serve: number of requests")
     ap.add_argument("--max-dim", type=int, default=65536, help="serve: largest m, n")
+    ap.add_argument("--serve-kmax", type=int, default=64, help="serve: rank cap of the adaptive growth")
     ap.add_argument("--phases", type=int, default=4, help="serve: phases per request per tick")
     ap.add_argument("--budget-gib", type=int, default=64, help="serve: HBM budget of the serving context")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-samples", type=int, default=20)
+    ap.add_argument("--threads", type=int, default=0, help="host threads of the oracle baselines (0: cores, <= 16)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--team", type=int, default=0)
@@ -559,7 +695,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
-    if args.workload == "dense":
+    if args.workload == "all":
+        out = bench_all(args)
+    elif args.workload == "dense":
         out = bench_dense(args)
     elif args.workload == "plain":
         out = bench_dense(args, plain=True)
@@ -570,6 +708,15 @@ def main():
     else:
         out = bench_serve(args)
     print(json.dumps(out), flush=True)
+    # explicit teardown before the interpreter exits: every context is closed
+    # inside its leg; drop the cached input and torch's cached device memory
+    import gc
+    import torch
+    torch.cuda.synchronize()
+    _DENSE_CACHE.clear()
+    gc.collect()
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
