@@ -104,6 +104,18 @@ typedef struct lra_options {
                                     from stream seed+1 and sort                             */
     const int64_t* sample_cols;  /* host, optional: S (sample_s distinct cols); NULL: draw
                                     from stream seed+2 and sort                             */
+    /* The fixed-rank CUR algorithms compared by the C-A tests (Section 12.2)
+     * and the Primitive algorithm (Section 6.5); all need tol <= 0.          */
+    int32_t cur_rank;            /* Cynical step (Tests 3, 4): after the sweeps, an r x r
+                                    generator of locally maximal volume inside the k x k
+                                    one, by C-A sweeps on that block; 0 or k: none (0)     */
+    int32_t inner_sweeps;        /* sweeps of the Cynical step inside the block, stopping
+                                    once one changes nothing (4)                           */
+    int32_t nucleus_rank;        /* Primitive nucleus U = (A[I,J])_r^+, the rank-r
+                                    truncated pseudo-inverse; 0 or k: A[I,J]^{-1} (0)      */
+    int32_t reserved2;
+    const int64_t* init_rows;    /* host, optional, sweeps = 0 only: the k random rows I
+                                    (distinct); NULL: drawn from stream seed+3              */
 } lra_options;
 
 /* Results.  I, J, G, U are caller-owned HOST arrays with capacity
@@ -162,11 +174,18 @@ void lra_destroy(lra_ctx* ctx);
 /* C-A / CUR of one m x n matrix (Section 6.5): `sweeps` sweeps of one column
  * step (maxvol on A[:,J] -> I) and one row step (maxvol on A[I,:]^T -> J)
  * from J0, then the nucleus U = A[I,J]^{-1} and the sampled residual
- * (Appendix F).  tol <= 0: exactly `sweeps` sweeps at rank k.  tol > 0:
+ * (Appendix F).  sweeps = 0 (tol <= 0): no C-A step, I = opts->init_rows
+ * and J = J0 at random (Section 12.2, Tests 1; with cur_rank the random
+ * p x q submatrix of Tests 3; with nucleus_rank the Primitive algorithm).
+ * opts->cur_rank and opts->nucleus_rank select the Cynical step and the
+ * truncated nucleus (see lra_options; the result then has rank cur_rank,
+ * resp. k with a rank-nucleus_rank nucleus).  tol <= 0: exactly `sweeps`
+ * sweeps at rank k.  tol > 0:
  * per rank level up to `sweeps` sweeps (stopping once a sweep leaves (I, J)
  * unchanged); if the estimate exceeds tol and k < k_max, k_step new
  * candidate columns are appended and the level restarts from a fresh LU.
- * Requires 1 <= k <= min(m, n, 64), k_max <= 64.
+ * Requires 1 <= k <= min(m, n, 64), k_max <= 64, sweeps >= 0 (0 only with
+ * tol <= 0).
  * Errors: LRA_EINVAL, LRA_ERANK, LRA_ENONFINITE, LRA_ENOMEM, LRA_EBUDGET,
  * LRA_EDEVICE. */
 lra_status lra_ca_cur(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k,

@@ -1551,6 +1551,134 @@ DI void block_sums(double (&v)[NV], Smem<T, KMAX>& sm)
 // nucleus U = A[I,J]^{-1} and the sampled residual (leader workgroup only)
 // ----------------------------------------------------------------------------
 
+// The Primitive algorithm's nucleus (Section 6.5): U = (G)_r^+, the
+// pseudo-inverse of the rank-r truncation of the generator, by the one-sided
+// Jacobi method (Hestenes): W = G V with V = I at the start, rotating column
+// pairs of W and V until every pair is orthogonal to working precision
+// (|w_p . w_q| <= k u ||w_p|| ||w_q||, at most 100 sweeps).  Each sweep is a
+// round-robin tournament of k - 1 rounds (k + 1 for odd k, with a padding
+// column that is never rotated); in a round, disjoint pairs rotate at once,
+// one pair per group of 8 lanes.  Then sigma_j = ||W[:,j]||, and with the
+// r largest (ties: smaller j) U[a][b] = sum_t V[a][j_t] W[b][j_t] / sigma^2.
+// F = [G | I | A[I,S]] (row stride LDF) on entry; on exit the middle block
+// holds U and the right block U A[I,S]; sm.ok = (sigma_{j_r} > 0).
+template <typename T, int KMAX, int LDF>
+DI void jacobi_pinv(double* F, int k, int r, int s, Smem<T, KMAX>& sm)
+{
+    const int kk = k + (k & 1);
+    const int npair = kk / 2;
+    const int grp = threadIdx.x >> 3, g8 = threadIdx.x & 7;
+    const double eps = (double)k * 0x1p-53;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        if (threadIdx.x == 0) sm.flag = 0;
+        __syncthreads();
+        for (int round = 0; round < kk - 1; ++round) {
+            if (grp < npair) {
+                const int a = grp, b = kk - 1 - grp;
+                const int pa = a == 0 ? 0 : (a - 1 + round) % (kk - 1) + 1;
+                const int pb = (b - 1 + round) % (kk - 1) + 1;
+                const int P = pa < pb ? pa : pb, Qc = pa < pb ? pb : pa;
+                if (Qc < k) {
+                    double al = 0.0, be = 0.0, ga = 0.0;
+                    for (int i = g8; i < k; i += 8) {
+                        const double wp = F[i * LDF + P], wq = F[i * LDF + Qc];
+                        al += wp * wp;
+                        be += wq * wq;
+                        ga += wp * wq;
+                    }
+#pragma unroll
+                    for (int o = 4; o >= 1; o >>= 1) {
+                        al += __shfl_xor(al, o, 64);
+                        be += __shfl_xor(be, o, 64);
+                        ga += __shfl_xor(ga, o, 64);
+                    }
+                    if (fabs(ga) > eps * sqrt(al * be)) {
+                        const double zeta = (be - al) / (2.0 * ga);
+                        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        const double c = 1.0 / sqrt(1.0 + t * t);
+                        const double sn = c * t;
+                        for (int i = g8; i < k; i += 8) {
+                            const double wp = F[i * LDF + P], wq = F[i * LDF + Qc];
+                            F[i * LDF + P] = c * wp - sn * wq;
+                            F[i * LDF + Qc] = sn * wp + c * wq;
+                            const double vp = F[i * LDF + KMAX + P], vq = F[i * LDF + KMAX + Qc];
+                            F[i * LDF + KMAX + P] = c * vp - sn * vq;
+                            F[i * LDF + KMAX + Qc] = sn * vp + c * vq;
+                        }
+                        if (g8 == 0) sm.flag = 1;
+                    }
+                }
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+        const int rotated = sm.flag;
+        __syncthreads();
+        if (!rotated) break;
+    }
+    // singular values and their order (decreasing; ties by index)
+    double* sv = sm.pts;
+    if (threadIdx.x < k) {
+        double s2 = 0.0;
+        for (int i = 0; i < k; ++i) s2 += F[i * LDF + threadIdx.x] * F[i * LDF + threadIdx.x];
+        sv[threadIdx.x] = sqrt(s2);
+    }
+    __syncthreads();
+    if (threadIdx.x < k) {
+        const int j = threadIdx.x;
+        int pos = 0;
+        for (int i = 0; i < k; ++i) pos += (sv[i] > sv[j] || (sv[i] == sv[j] && i < j)) ? 1 : 0;
+        sm.perm[pos] = j;
+    }
+    __syncthreads();
+    constexpr int PE = (KMAX * KMAX + NT - 1) / NT;
+    double u[PE];
+#pragma unroll
+    for (int q = 0; q < PE; ++q) {
+        const int e = threadIdx.x + q * NT;
+        double acc = 0.0;
+        if (e < k * k) {
+            const int a = e / k, b = e % k;
+            for (int t = 0; t < r; ++t) {
+                const int j = sm.perm[t];
+                acc += F[a * LDF + KMAX + j] * (F[b * LDF + j] / (sv[j] * sv[j]));
+            }
+        }
+        u[q] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PE; ++q) {
+        const int e = threadIdx.x + q * NT;
+        if (e < k * k) F[(e / k) * LDF + KMAX + e % k] = u[q];
+    }
+    __threadfence_block();
+    __syncthreads();
+    // U A[I,S] over the right block (A[I,S] read before any of it is overwritten;
+    // k s <= 64 KMAX entries)
+    constexpr int PW = (KMAX * 64 + NT - 1) / NT;
+    double w[PW];
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+        const int e = threadIdx.x + q * NT;
+        double acc = 0.0;
+        if (e < k * s) {
+            const int a = e / s, b = e % s;
+            for (int c = 0; c < k; ++c) acc += F[a * LDF + KMAX + c] * F[c * LDF + KMAX + k + b];
+        }
+        w[q] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PW; ++q) {
+        const int e = threadIdx.x + q * NT;
+        if (e < k * s) F[(e / s) * LDF + KMAX + k + e % s] = w[q];
+    }
+    if (threadIdx.x == 0) sm.ok = sv[sm.perm[r - 1]] > 0.0 ? 1 : 0;
+    __threadfence_block();
+    __syncthreads();
+}
+
 // FLDS: the work matrices fit the workgroup's LDS (else they live in the
 // problem's global work buffer); a compile-time choice keeps LDS accesses
 // ds_* instructions.
@@ -1567,6 +1695,7 @@ DI void final_core(const TaskDesc& td, Team& tio)
     const GL int64_t* const Qi = gl(td.Q);
     const GL int64_t* const Si = gl(td.S);
     const DevSource src = td.src;
+    const int ntr = td.nucleus_rank;
     // F = [G | I | A[I,S]] (row stride LDF; s <= 64), then A[Q,J] and A[Q,S]
     constexpr int LDF = 2 * KMAX + 64;
     double* Fm = FLDS ? (double*)blds_ptr<T, KMAX>() : td.work;
@@ -1606,7 +1735,24 @@ DI void final_core(const TaskDesc& td, Team& tio)
     // wavefront 3 fetches A[Q,J] and A[Q,S].  Larger k: one solve on
     // wavefront 0, the fetches on the other three.
     constexpr int K32 = KMAX < 32 ? KMAX : 32;
-    if (k <= K32 && s <= 64) {
+    if (ntr > 0 && ntr < k) {
+        // truncated nucleus: the sample blocks first, then the SVD
+        load_entries<double, 8>(
+            src, q * k, threadIdx.x, NT,
+            [&](int e, int64_t& i, int64_t& j) {
+                i = Qi[e / k];
+                j = sm.J[e % k];
+            },
+            [&](int e, double v) { AQJ[e] = v; });
+        load_entries<double, 8>(
+            src, q * s, threadIdx.x, NT,
+            [&](int e, int64_t& i, int64_t& j) {
+                i = Qi[e / s];
+                j = Si[e % s];
+            },
+            [&](int e, double v) { E[e] = v; });
+        jacobi_pinv<T, KMAX, LDF>(Fm, k, ntr, s, sm);
+    } else if (k <= K32 && s <= 64) {
         const int wv = threadIdx.x >> 6;
         if (wv == 0) {
             lu_solve_wave0<T, KMAX, double, LDF, (2 * KMAX + 127) / 64, 1>(Fm, k, KMAX, k, sm);
@@ -1779,6 +1925,112 @@ NOINL void final_leader(const TaskDesc& td, Team& tio, int lds_b_bytes)
 }
 
 // ----------------------------------------------------------------------------
+// the Cynical step (Section 6.5; Section 12.2, Tests 3 and 4): an r x r
+// submatrix of locally maximal volume inside the k x k generator A[K, L]
+// (leader workgroup only)
+// ----------------------------------------------------------------------------
+//
+// The block A[K, L] is gathered once into the problem's work buffer (strip
+// precision, row-major k x k) and becomes a dense source of its own; dual C-A
+// sweeps at rank r run on it from J0 = its first r columns, with the same
+// maxvol steps as the sweeps on A (a team of one workgroup), until a sweep
+// after the first changes nothing or inner_sweeps sweeps are done.  The local
+// indices are then mapped back through K and L.  Entries read from A: the
+// k^2 of the block (the inner steps read the block only).
+template <typename T, int KMAX>
+NOINL void reduce_leader(const TaskDesc& td, Team& tio, int lds_b_bytes)
+{
+    Team one = tio;
+    one.size = 1;
+    one.rank = 0;
+    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
+    const int p = sm.k;
+    const int r = td.cur_rank;
+    const int inner = td.inner_sweeps;
+    const int64_t er0 = sm.entries_read;
+    // descriptor fields read before any store (a store could alias them)
+    TaskDesc sub = td;
+    T* blk = (T*)td.work;
+    int64_t* KL = (int64_t*)(blk + ((int64_t)p * p + 1) / 2 * 2);
+    T* sstrip = (T*)(KL + 2 * KMAX);
+    if (threadIdx.x < p) {
+        gl(KL)[threadIdx.x] = sm.I[threadIdx.x];
+        gl(KL)[KMAX + threadIdx.x] = sm.J[threadIdx.x];
+    }
+    load_entries<T, (KMAX * KMAX + NT - 1) / NT>(
+        td.src, p * p, threadIdx.x, NT,
+        [&](int e, int64_t& i, int64_t& j) {
+            i = sm.I[e / p];
+            j = sm.J[e % p];
+        },
+        [&](int e, T v) { gl(blk)[e] = v; });
+    __threadfence_block();
+    __syncthreads();
+    sub.src.kind = 0;
+    sub.src.dtype = sizeof(T) == 8 ? 1 : 0;
+    sub.src.a = blk;
+    sub.src.lda = p;
+    sub.src.col_major = 0;
+    sub.src.x = nullptr;
+    sub.src.y = nullptr;
+    sub.m = p;
+    sub.n = p;
+    sub.strip = sstrip;
+    if (threadIdx.x == 0) {
+        sm.k = r;
+        sm.have_I = 0;
+    }
+    if (threadIdx.x < r) sm.J[threadIdx.x] = threadIdx.x;
+    __syncthreads();
+    const bool lds = (int64_t)p * r * (int64_t)sizeof(T) <= lds_b_bytes;
+    for (int it = 0; it < inner; ++it) {
+        const int k_before = sm.k, had = sm.have_I;
+        if (threadIdx.x < k_before) {
+            sm.prevI[threadIdx.x] = sm.I[threadIdx.x];
+            sm.prevJ[threadIdx.x] = sm.J[threadIdx.x];
+        }
+        __syncthreads();
+        if (lds) maxvol_step<T, KMAX, true>(sub, one, 0);
+        else maxvol_step<T, KMAX, false>(sub, one, 0);
+        if (sm.phase == PH_DONE) break;
+        if (threadIdx.x == 0) sm.have_I = 1;
+        __syncthreads();
+        if (lds) maxvol_step<T, KMAX, true>(sub, one, 1);
+        else maxvol_step<T, KMAX, false>(sub, one, 1);
+        if (sm.phase == PH_DONE) break;
+        if (had && sm.k == k_before) {
+            if (threadIdx.x == 0) {
+                int same = 1;
+                for (int c = 0; c < sm.k; ++c)
+                    if (sm.I[c] != sm.prevI[c] || sm.J[c] != sm.prevJ[c]) same = 0;
+                sm.flag = same;
+            }
+            __syncthreads();
+            const int same = sm.flag;
+            __syncthreads();
+            if (same) break;
+        }
+    }
+    __syncthreads();
+    if (sm.phase != PH_DONE) {
+        const int kf = sm.k;
+        if (threadIdx.x < kf) {
+            const int64_t il = sm.I[threadIdx.x], jl = sm.J[threadIdx.x];
+            sm.I[threadIdx.x] = gl(KL)[il];
+            sm.J[threadIdx.x] = gl(KL)[KMAX + jl];
+        }
+        if (threadIdx.x == 0) {
+            sm.entries_read = er0 + (int64_t)p * p;
+            sm.have_I = 1;
+            sm.phase = PH_FINAL;
+        }
+    }
+    __syncthreads();
+    tio.tog = one.tog;
+    tio.trace_n = one.trace_n;
+}
+
+// ----------------------------------------------------------------------------
 // state transfer between the team's workgroups and across launches
 // ----------------------------------------------------------------------------
 
@@ -1934,7 +2186,8 @@ DI void run_task(const TaskDesc& td, Team& tm, const EngineArgs& ea)
             if (threadIdx.x == 0 && sm.phase != PH_DONE) {
                 sm.sweeps_done += 1;
                 sm.sweep_in_level += 1;
-                int next = sm.sweep_in_level >= td.sweeps ? PH_FINAL : PH_COL;
+                const int after = (td.cur_rank > 0 && td.cur_rank < sm.k) ? PH_REDUCE : PH_FINAL;
+                int next = sm.sweep_in_level >= td.sweeps ? after : PH_COL;
                 if (td.tol > 0.0 && sm.had_I_sweep && sm.k == sm.k_sweep_start) {
                     int same = 1;
                     for (int c = 0; c < sm.k; ++c)
@@ -1944,6 +2197,15 @@ DI void run_task(const TaskDesc& td, Team& tm, const EngineArgs& ea)
                 sm.phase = next;
             }
             __syncthreads();
+        } else if (ph == PH_REDUCE) {
+            if (tm.rank == 0) reduce_leader<T, KMAX>(td, tm, lds_b);
+            if (tm.size > 1) {
+                // the leader's generator reaches the team through global memory
+                if (tm.rank == 0) store_state(td, sm);
+                team_barrier(tm);
+                if (tm.failed) return;
+                if (tm.rank != 0) load_state(td, sm);
+            }
         } else {  // PH_FINAL
             trace_ev(tm, EV_FINAL_BEGIN, 0);
             write_factors<T, KMAX>(td, sm, tm);

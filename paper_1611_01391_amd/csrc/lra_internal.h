@@ -17,7 +17,8 @@ struct DevSource {
     const void* y;
 };
 
-enum Phase : int32_t { PH_COL = 0, PH_ROW = 1, PH_FINAL = 2, PH_DONE = 3 };
+// PH_REDUCE: the Cynical step (an r x r generator inside the k x k one).
+enum Phase : int32_t { PH_COL = 0, PH_ROW = 1, PH_FINAL = 2, PH_DONE = 3, PH_REDUCE = 4 };
 
 enum Warn : int32_t { W_TOL = 1, W_CAP = 2, W_NUMRANK = 4 };
 
@@ -65,7 +66,9 @@ struct TaskDesc {
     void* R_out;       // optional: A[I,:], k x n row-major, strip precision
     TaskState* st;
     int32_t variant;   // kernel variant: 4 * (binary64 strips) + log2(KMAX / 8)
-    int32_t pad_v;
+    int32_t cur_rank;      // Cynical reduction to this rank after the sweeps (0: none)
+    int32_t inner_sweeps;  // C-A sweeps of the reduction inside the k x k block
+    int32_t nucleus_rank;  // truncated pseudo-inverse nucleus of this rank (0: inverse)
 };
 
 constexpr int NVARIANT = 8;

@@ -187,6 +187,10 @@ extern "C" void lra_default_options(lra_options* o)
     o->sample_s = 64;
     o->team_wgs = 0;
     o->seed = 0;
+    o->cur_rank = 0;
+    o->inner_sweeps = 4;
+    o->nucleus_rank = 0;
+    o->init_rows = nullptr;
 }
 
 extern "C" const char* lra_status_str(lra_status s)
@@ -290,12 +294,19 @@ struct Prob {
     void* R_out = nullptr;
     bool have_init_I = false;
     std::vector<int64_t> init_I;
+    int cur_rank = 0, inner_sweeps = 4, nucleus_rank = 0;
 };
 
 static lra_status make_prob(const lra_source* src, int64_t m, int64_t n, int k, int sweeps, double tol,
                             const lra_options* o, Prob& p, int64_t blk_index)
 {
-    if (!src_ok(src) || m < 1 || n < 1 || k < 1 || k > 64 || k > m || k > n || sweeps < 1) return LRA_EINVAL;
+    if (!src_ok(src) || m < 1 || n < 1 || k < 1 || k > 64 || k > m || k > n || sweeps < 0) return LRA_EINVAL;
+    // the fixed-rank algorithms (random sets, Cynical step, truncated nucleus) take no tolerance
+    if (o->cur_rank < 0 || o->cur_rank > k || o->nucleus_rank < 0 || o->nucleus_rank > k) return LRA_EINVAL;
+    const bool fixed_alg = sweeps == 0 || (o->cur_rank > 0 && o->cur_rank < k) ||
+                           (o->nucleus_rank > 0 && o->nucleus_rank < k);
+    if (fixed_alg && tol > 0.0) return LRA_EINVAL;
+    if (o->cur_rank > 0 && o->cur_rank < k && o->inner_sweeps < 1) return LRA_EINVAL;
     if (!(o->tau >= 0.0) || o->k_step < 1 || o->k_max > 64) return LRA_EINVAL;
     if (src->kind == LRA_SRC_DENSE && src->lda < (src->col_major ? m : n)) return LRA_EINVAL;
     if (o->precision != LRA_PREC_FP64 && o->precision != LRA_PREC_MIXED) return LRA_EINVAL;
@@ -351,6 +362,24 @@ static lra_status make_prob(const lra_source* src, int64_t m, int64_t n, int k, 
         if (v < 0 || v >= m) return LRA_EINVAL;
     for (int64_t v : p.S)
         if (v < 0 || v >= n) return LRA_EINVAL;
+    p.cur_rank = o->cur_rank < k ? o->cur_rank : 0;
+    p.inner_sweeps = o->inner_sweeps;
+    p.nucleus_rank = o->nucleus_rank < k ? o->nucleus_rank : 0;
+    if (sweeps == 0) {
+        // random rows of the generator: the caller's, or drawn from stream seed+3
+        p.have_init_I = true;
+        if (o->init_rows) {
+            p.init_I.assign(o->init_rows, o->init_rows + k);
+            for (int a = 0; a < k; ++a) {
+                if (p.init_I[a] < 0 || p.init_I[a] >= m) return LRA_EINVAL;
+                for (int b = a + 1; b < k; ++b)
+                    if (p.init_I[a] == p.init_I[b]) return LRA_EINVAL;
+            }
+        } else {
+            p.init_I.resize(k);
+            draw_distinct(seed + 3, m, k, p.init_I.data());
+        }
+    }
     return LRA_OK;
 }
 
@@ -409,7 +438,10 @@ struct ProbRegions {
 static int64_t work_bytes(const Prob& p)
 {
     const int64_t kb = kmax_bucket(p.kcap), kc = p.kcap;
-    return 8 * (kb * (2 * kb + 64) + (int64_t)p.q * kc + (int64_t)p.q * p.s);
+    const int64_t fin = 8 * (kb * (2 * kb + 64) + (int64_t)p.q * kc + (int64_t)p.q * p.s);
+    // Cynical step: the k x k block, K and L (2 KMAX), a k x r strip
+    const int64_t red = 8 * (kc * kc + 2 + 2 * kb + kc * kc);
+    return std::max(fin, red);
 }
 
 static int64_t strip_bytes(const Prob& p, int prec64)
@@ -448,7 +480,9 @@ static void fill_task(TaskDesc& td, const Prob& p, uint8_t* base, const ProbRegi
     td.R_out = p.R_out;
     td.st = (TaskState*)(base + r.st);
     td.variant = variant_index(p.prec64, p.kmx);
-    td.pad_v = 0;
+    td.cur_rank = p.cur_rank;
+    td.inner_sweeps = p.inner_sweeps;
+    td.nucleus_rank = p.nucleus_rank;
 }
 
 // Host image of the inputs (cand, Q, S) and of the initial state (st, I, J).
@@ -469,7 +503,8 @@ static void init_state(uint8_t* h_st, uint8_t* h_I, uint8_t* h_J, const Prob& p)
     }
     TaskState* st = (TaskState*)h_st;
     std::memset(st, 0, sizeof(*st));
-    st->phase = PH_COL;
+    // no C-A sweeps: straight to the Cynical step or the nucleus
+    st->phase = p.sweeps > 0 ? PH_COL : (p.cur_rank > 0 ? PH_REDUCE : PH_FINAL);
     st->k = p.k;
     st->have_I = p.have_init_I ? 1 : 0;
     st->cand_next = p.k;
@@ -1055,7 +1090,7 @@ extern "C" lra_status lra_ca_cur_batched(lra_ctx* ctx, const lra_block* blocks, 
     lra_options o;
     if (opts) o = *opts;
     else lra_default_options(&o);
-    if (o.init_cols || o.sample_rows || o.sample_cols) return LRA_EINVAL;
+    if (o.init_cols || o.sample_rows || o.sample_cols || o.init_rows) return LRA_EINVAL;
     const int prec64 = o.precision == LRA_PREC_FP64;
     std::vector<Prob> probs(nblocks);
     std::vector<lra_result*> rp(nblocks);

@@ -51,7 +51,8 @@ class Options(C.Structure):
                 ("sample_q", C.c_int32), ("sample_s", C.c_int32), ("team_wgs", C.c_int32),
                 ("reserved", C.c_int32), ("seed", C.c_uint64), ("init_cols", C.c_void_p),
                 ("n_init_cols", C.c_int64), ("sample_rows", C.c_void_p),
-                ("sample_cols", C.c_void_p)]
+                ("sample_cols", C.c_void_p), ("cur_rank", C.c_int32), ("inner_sweeps", C.c_int32),
+                ("nucleus_rank", C.c_int32), ("reserved2", C.c_int32), ("init_rows", C.c_void_p)]
 
 
 class ResultC(C.Structure):
@@ -269,6 +270,28 @@ def _i64(a) -> Optional[np.ndarray]:
     return np.ascontiguousarray(np.asarray(a, dtype=np.int64))
 
 
+def _options(opts: dict, init_cols=None, sample_rows=None, sample_cols=None):
+    """lra_options from keyword options; host index arrays (init_cols,
+    sample_rows, sample_cols, init_rows) are converted and returned with the
+    struct so that they outlive the call."""
+    opts = dict(opts)
+    rows = _i64(opts.pop("init_rows", None))
+    o = default_options(**opts)
+    cand, Q, S = _i64(init_cols), _i64(sample_rows), _i64(sample_cols)
+    if cand is not None:
+        o.init_cols = cand.ctypes.data
+        o.n_init_cols = len(cand)
+    if Q is not None:
+        o.sample_rows = Q.ctypes.data
+        o.sample_q = len(Q)
+    if S is not None:
+        o.sample_cols = S.ctypes.data
+        o.sample_s = len(S)
+    if rows is not None:
+        o.init_rows = rows.ctypes.data
+    return o, (cand, Q, S, rows)
+
+
 # ---------------------------------------------------------------------------
 # context
 # ---------------------------------------------------------------------------
@@ -330,17 +353,7 @@ class Context:
     def _ca_cur(self, fn, src, k, sweeps, tol, init_cols, sample_rows, sample_cols, factors, raise_on_error,
                 opts) -> Result:
         import torch
-        o = default_options(**opts)
-        cand, Q, S = _i64(init_cols), _i64(sample_rows), _i64(sample_cols)
-        if cand is not None:
-            o.init_cols = cand.ctypes.data
-            o.n_init_cols = len(cand)
-        if Q is not None:
-            o.sample_rows = Q.ctypes.data
-            o.sample_q = len(Q)
-        if S is not None:
-            o.sample_cols = S.ctypes.data
-            o.sample_s = len(S)
+        o, keep = _options(opts, init_cols, sample_rows, sample_cols)
         kcap = max(k, o.k_max)
         buf = _ResultBuf(kcap)
         C_t = R_t = None
@@ -389,17 +402,7 @@ class Context:
     def autotune_team(self, src: DeviceSource, k: int, sweeps: int, tol: float = 0.0, *,
                       init_cols=None, sample_rows=None, sample_cols=None, **opts):
         """Time team sizes for problems of this size class; returns (team, ms)."""
-        o = default_options(**opts)
-        cand, Q, S = _i64(init_cols), _i64(sample_rows), _i64(sample_cols)
-        if cand is not None:
-            o.init_cols = cand.ctypes.data
-            o.n_init_cols = len(cand)
-        if Q is not None:
-            o.sample_rows = Q.ctypes.data
-            o.sample_q = len(Q)
-        if S is not None:
-            o.sample_cols = S.ctypes.data
-            o.sample_s = len(S)
+        o, keep = _options(opts, init_cols, sample_rows, sample_cols)
         team = C.c_int(0)
         ms = C.c_double(0.0)
         st = lib().lra_autotune_team(self._h, C.byref(src.struct), src.m, src.n, int(k), int(sweeps),
@@ -492,17 +495,7 @@ class Context:
     def submit(self, src: DeviceSource, k: int, sweeps: int, tol: float = 0.0, *,
                init_cols=None, sample_rows=None, sample_cols=None, **opts) -> int:
         """Queue one request; returns its ticket (see poll / wait)."""
-        o = default_options(**opts)
-        cand, Q, S = _i64(init_cols), _i64(sample_rows), _i64(sample_cols)
-        if cand is not None:
-            o.init_cols = cand.ctypes.data
-            o.n_init_cols = len(cand)
-        if Q is not None:
-            o.sample_rows = Q.ctypes.data
-            o.sample_q = len(Q)
-        if S is not None:
-            o.sample_cols = S.ctypes.data
-            o.sample_s = len(S)
+        o, keep = _options(opts, init_cols, sample_rows, sample_cols)
         buf = _ResultBuf(max(int(k), o.k_max))
         req = RequestC()
         req.src = src.struct
