@@ -268,9 +268,44 @@ def bench_dense(args, plain=False):
     out["parity"] = parity
     out["result"] = {"status": int(res.status), "k": int(res.k), "swaps": int(res.swaps_total),
                      "est_rel": res.err_est_rel, "entries_read": int(res.entries_read)}
+    if not plain:
+        out["strip_gather"] = _strip_gather(ctx, torch, src, n, n, res, esz)
     ctx.close()
     del At
     return out
+
+
+def _strip_gather(ctx, torch, src, m, n, res, esz, reps=50):
+    """The strip gather on its own: lra_cur_factors writes C = A[:, J] and
+    R = A[I, :] for the run's final sets (one column strip and one row strip
+    of the workload, in the source precision), timed with HIP events.  The
+    algorithmic bytes are the strips read and written; the DRAM bytes come
+    from the committed FETCH_SIZE / WRITE_SIZE counters of the same kernel."""
+    dt = torch.float32 if esz == 4 else torch.float64
+    k = res.k
+    Cb = torch.empty(k * m, dtype=dt, device="cuda")
+    Rb = torch.empty(k * n, dtype=dt, device="cuda")
+    for _ in range(3):
+        ctx.cur_factors(src, res.I, res.J, dtype=dt, C_out=Cb, R_out=Rb)
+    torch.cuda.synchronize()
+    ctx.set_timing(True, reset=True)
+    for _ in range(reps):
+        ctx.cur_factors(src, res.I, res.J, dtype=dt, C_out=Cb, R_out=Rb)
+    st = ctx.stats()
+    ctx.set_timing(False, reset=False)
+    kms = st["engine_ms_total"] / max(1, st["launches"])
+    alg = 2 * (m * k + k * n) * esz
+    dram = _profiled("factors_kernel_dense16384_k32.md", "traffic_bytes_per_launch")
+    g = {"kernel": "factors_kernel", "kernel_ms": kms, "algorithmic_bytes": alg,
+         "achieved_GBps": alg / (kms * 1e-3) / 1e9, "frac_algorithmic": alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+         "dram_bytes": dram, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "note": "one m x k column strip and one k x n row strip of the workload, read and written"}
+    if dram:
+        g["dram_GBps"] = dram / (kms * 1e-3) / 1e9
+        g["frac_dram"] = g["dram_GBps"] / HBM_PEAK_GBS
+    log(f"# strip gather: {kms * 1e3:.1f} us, {g['achieved_GBps']:.0f} GB/s algorithmic"
+        + (f", {g['dram_GBps']:.0f} GB/s DRAM" if dram else ""))
+    return g
 
 
 # ---------------------------------------------------------------------------
@@ -645,7 +680,7 @@ def bench_all(args):
     t0 = time.time()
     out = _leg("dense fp64", bench_dense, args)
     keep = ("value", "unit", "ms_per_step", "steps", "warmup", "dtype", "config", "roofline", "cpu_baseline",
-            "parity", "result", "wall_s")
+            "parity", "result", "strip_gather", "wall_s")
     mixed = _leg("dense mixed", bench_dense, args, precision="mixed", steps=10, warmup=2)
     out["mixed_path"] = _summary(mixed, keep)
     plain = _leg("plain 512", lambda a: bench_dense(a, plain=True), args, steps=50, warmup=5)

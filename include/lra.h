@@ -167,7 +167,11 @@ void lra_default_options(lra_options* opts);
 
 /* Create a context on the current HIP device.  stream: a hipStream_t (NULL =
  * the null stream).  hbm_budget_bytes bounds the device workspace the
- * context may hold (0 = no bound).  Errors: LRA_EDEVICE, LRA_ENOMEM. */
+ * context may hold (0 = no bound): the workspace of the blocking calls, the
+ * serving arena and its control images together.  The workspace grows on
+ * demand (by the first call of a larger size; later calls no larger than an
+ * earlier one allocate nothing); lra_ca_cur_noalloc never allocates.
+ * Errors: LRA_EDEVICE, LRA_ENOMEM. */
 lra_status lra_create(lra_ctx** ctx, void* stream, size_t hbm_budget_bytes);
 void lra_destroy(lra_ctx* ctx);
 
@@ -212,6 +216,19 @@ lra_status lra_ca_cur(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n,
 #define LRA_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
 lra_status lra_ca_cur_noalloc(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k,
                               int sweeps, double tol, const lra_options* opts, lra_result* result);
+
+/* The CUR factors of given row and column sets (Section 6.5: C = M_{:,J},
+ * R = M_{I,:}): C = A[:,J] (m x k, column-major, m k elements) and
+ * R = A[I,:] (k x n, row-major, k n elements) written into caller-owned
+ * device buffers (either may be NULL) in out_dtype (LRA_F32 or LRA_F64),
+ * by one kernel over the whole device.  I, J: host arrays of k indices
+ * (0 <= I[c] < m, 0 <= J[c] < n; repeats allowed).  Generated sources give
+ * the generated entries.  Returns after the factors are written.  With
+ * timing enabled (lra_set_timing) the kernel is timed like an engine launch.
+ * Errors: LRA_EINVAL (also when m k or k n reaches 2^31), LRA_ENOMEM,
+ * LRA_EBUDGET, LRA_EDEVICE. */
+lra_status lra_cur_factors(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k,
+                           const int64_t* I, const int64_t* J, int32_t out_dtype, void* C_out, void* R_out);
 
 /* The maxvol sub-algorithm alone on a tall device strip (m x k, column-major,
  * leading dimension ld >= m, element type `dtype`): locally maximal-volume
@@ -298,6 +315,11 @@ typedef struct lra_stats {
     int32_t last_grid;           /* workgroups of the latest launch          */
     int32_t last_teams;          /* teams of the latest launch               */
     int64_t ticks;               /* serving ticks                            */
+    int64_t device_allocs;       /* device allocations since creation (never
+                                    reset; a call no larger than an earlier
+                                    one makes none)                          */
+    int64_t device_bytes;        /* device bytes the context holds now (never
+                                    above hbm_budget_bytes when one is set)  */
 } lra_stats;
 /* enable: 1 on, 0 off; reset: zero the counters. */
 lra_status lra_set_timing(lra_ctx* ctx, int enable, int reset);

@@ -2297,6 +2297,42 @@ __global__ __launch_bounds__(NT) void engine_kernel_all(EngineArgs ea)
     });
 }
 
+// The CUR factors of given index sets (Section 6.5): C = A[:, J] (m x k,
+// column-major) and R = A[I, :] (k x n, row-major), by the whole grid.
+// Entry e of C is C[e] = A[e % m, J[e / m]] and entry e of R is
+// R[e] = A[I[e / n], e % n], so consecutive threads write consecutive
+// addresses; each thread keeps 8 entries' loads in flight.  A column of a
+// row-major matrix has one entry per memory line: that gather is bound by
+// line fetches, the row gather by its bytes.
+template <typename T>
+__global__ __launch_bounds__(256) void factors_kernel(DevSource src, int64_t m, int64_t n, int k,
+                                                      const int64_t* I, const int64_t* J, T* C, T* R)
+{
+    const int tid = (int)(blockIdx.x * 256 + threadIdx.x), nth = (int)(gridDim.x * 256);
+    const GL int64_t* Ig = gl(I);
+    const GL int64_t* Jg = gl(J);
+    if (C) {
+        GL T* Cg = gl(C);
+        load_entries<T, 8>(
+            src, (int)(m * k), tid, nth,
+            [&](int e, int64_t& i, int64_t& j) {
+                i = e % m;
+                j = Jg[e / m];
+            },
+            [&](int e, T v) { Cg[e] = v; });
+    }
+    if (R) {
+        GL T* Rg = gl(R);
+        load_entries<T, 8>(
+            src, (int)(k * n), tid, nth,
+            [&](int e, int64_t& i, int64_t& j) {
+                i = Ig[e / n];
+                j = e % n;
+            },
+            [&](int e, T v) { Rg[e] = v; });
+    }
+}
+
 // Zero-fill used instead of hipMemsetAsync (safe to record in a graph).
 __global__ void zero_kernel(uint32_t* p, int64_t n_words)
 {
@@ -2353,6 +2389,22 @@ hipError_t launch_engine(int prec64, int kmax, int grid, size_t smem, bool coope
     void* args[] = {&a};
     if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(NT), args, (unsigned)smem, stream);
     return hipLaunchKernel(fn, dim3(grid), dim3(NT), args, smem, stream);
+}
+
+hipError_t launch_factors(const DevSource& src, int64_t m, int64_t n, int k, const int64_t* I, const int64_t* J,
+                          int out64, void* C, void* R, hipStream_t stream)
+{
+    const int64_t most = m * k > k * n ? m * k : k * n;
+    int64_t blocks = (most + 256 * 8 - 1) / (256 * 8);
+    if (blocks > 16384) blocks = 16384;
+    if (blocks < 1) blocks = 1;
+    if (out64)
+        hipLaunchKernelGGL(factors_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, stream, src, m, n, k, I, J,
+                           (double*)C, (double*)R);
+    else
+        hipLaunchKernelGGL(factors_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, stream, src, m, n, k, I, J,
+                           (float*)C, (float*)R);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t stream)

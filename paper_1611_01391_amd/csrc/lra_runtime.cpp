@@ -26,6 +26,8 @@ const void* engine_kernel_ptr(int prec64, int kmax);
 hipError_t launch_engine(int prec64, int kmax, int grid, size_t smem, bool cooperative,
                          const EngineArgs& ea, hipStream_t stream);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t stream);
+hipError_t launch_factors(const DevSource& src, int64_t m, int64_t n, int k, const int64_t* I, const int64_t* J,
+                          int out64, void* C, void* R, hipStream_t stream);
 hipError_t noalloc_scratch_init(int device);
 void* noalloc_scratch(int device);
 }  // namespace lra
@@ -130,7 +132,8 @@ struct lra_ctx {
     int lds_cap = 0;         // dynamic LDS per workgroup the kernels may use
     Buffer dev;              // workspace for blocking calls
     Buffer host;             // pinned staging for blocking calls
-    int64_t dev_in_use = 0;  // bytes held by the serving slots
+    int64_t dev_in_use = 0;  // device bytes held: blocking workspace, serving arena and control
+    int64_t dev_allocs = 0;  // device allocations made since creation
     std::map<std::string, int> tuned;  // autotuned team sizes by size class
     int64_t floor_rows = -1;           // autotuned planning floor (-1: default)
     bool timing = false;
@@ -152,18 +155,31 @@ static lra_status hip_fail(hipError_t e, const char* what)
         if (e_ != hipSuccess) return hip_fail(e_, #expr); \
     } while (0)
 
+// Grow a buffer to at least `bytes` (25% headroom, whole MiB).  Device
+// buffers count against the context's budget: what the other device buffers
+// hold plus the new size must fit, the headroom is clamped to what is left,
+// and the replaced buffer is freed first.  Steady-state calls (no larger
+// than an earlier one) allocate nothing.
 static lra_status ensure(Buffer& b, int64_t bytes, bool pinned, lra_ctx* ctx)
 {
     if (b.bytes >= bytes) return LRA_OK;
-    if (!pinned && ctx->budget && (size_t)(bytes + ctx->dev_in_use) > ctx->budget) return LRA_EBUDGET;
+    int64_t want = std::max<int64_t>(bytes, 1 << 20);
+    want = align_up(want + want / 4, 1 << 20);
+    if (!pinned && ctx->budget) {
+        const int64_t room = (int64_t)ctx->budget - (ctx->dev_in_use - b.bytes);
+        if (bytes > room) return LRA_EBUDGET;
+        want = std::min(want, room);
+    }
     if (b.p) {
-        if (pinned) (void)hipHostFree(b.p);
-        else (void)hipFree(b.p);
+        if (pinned) {
+            (void)hipHostFree(b.p);
+        } else {
+            (void)hipFree(b.p);
+            ctx->dev_in_use -= b.bytes;
+        }
         b.p = nullptr;
         b.bytes = 0;
     }
-    int64_t want = std::max<int64_t>(bytes, 1 << 20);
-    want = align_up(want + want / 4, 1 << 20);
     hipError_t e = pinned ? hipHostMalloc(&b.p, (size_t)want, hipHostMallocDefault) : hipMalloc(&b.p, (size_t)want);
     if (e != hipSuccess) {
         b.p = nullptr;
@@ -171,6 +187,10 @@ static lra_status ensure(Buffer& b, int64_t bytes, bool pinned, lra_ctx* ctx)
         return LRA_ENOMEM;
     }
     b.bytes = want;
+    if (!pinned) {
+        ctx->dev_in_use += want;
+        ctx->dev_allocs += 1;
+    }
     return LRA_OK;
 }
 
@@ -1031,6 +1051,50 @@ extern "C" lra_status lra_ca_cur_noalloc(lra_ctx* ctx, const lra_source* src, in
     return ca_cur_one(ctx, src, m, n, k, sweeps, tol, opts, result, &fb);
 }
 
+extern "C" lra_status lra_cur_factors(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k,
+                                      const int64_t* I, const int64_t* J, int32_t out_dtype, void* C_out,
+                                      void* R_out)
+{
+    if (!ctx || !src_ok(src) || m < 1 || n < 1 || k < 1 || !I || !J) return LRA_EINVAL;
+    if (out_dtype != LRA_F32 && out_dtype != LRA_F64) return LRA_EINVAL;
+    if (m * (int64_t)k >= ((int64_t)1 << 31) || n * (int64_t)k >= ((int64_t)1 << 31)) return LRA_EINVAL;
+    if (src->kind == LRA_SRC_DENSE && src->lda < (src->col_major ? m : n)) return LRA_EINVAL;
+    for (int c = 0; c < k; ++c)
+        if (I[c] < 0 || I[c] >= m || J[c] < 0 || J[c] >= n) return LRA_EINVAL;
+    if (!C_out && !R_out) return LRA_OK;
+    const int64_t bytes = 16 * (int64_t)k;
+    lra_status rs = ensure(ctx->dev, bytes, false, ctx);
+    if (rs != LRA_OK) return rs;
+    rs = ensure(ctx->host, bytes, true, ctx);
+    if (rs != LRA_OK) return rs;
+    int64_t* h = (int64_t*)ctx->host.p;
+    std::memcpy(h, I, 8 * (size_t)k);
+    std::memcpy(h + k, J, 8 * (size_t)k);
+    int64_t* d = (int64_t*)ctx->dev.p;
+    DevSource ds;
+    ds.kind = src->kind;
+    ds.dtype = src->dtype;
+    ds.a = src->a;
+    ds.lda = src->lda;
+    ds.col_major = src->col_major ? 1 : 0;
+    ds.pad = 0;
+    ds.x = src->x;
+    ds.y = src->y;
+    HIP_TRY(hipMemcpyAsync(d, h, (size_t)bytes, hipMemcpyHostToDevice, ctx->stream));
+    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev0, ctx->stream));
+    HIP_TRY(launch_factors(ds, m, n, k, d, d + k, out_dtype == LRA_F64, C_out, R_out, ctx->stream));
+    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev1, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->stats.launches += 1;
+    if (ctx->timing) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        ctx->stats.last_engine_ms = ms;
+        ctx->stats.engine_ms_total += ms;
+    }
+    return LRA_OK;
+}
+
 extern "C" lra_status lra_maxvol(lra_ctx* ctx, const void* strip, int32_t dtype, int64_t m, int64_t ld, int k,
                                  double tau, int max_swaps, const int64_t* init, int64_t* I, int* swaps, int* k_eff)
 {
@@ -1253,13 +1317,14 @@ static lra_status serve_init(lra_ctx* ctx)
     }
     s.table_bytes = align_up((int64_t)s.max_active * (int64_t)sizeof(TaskState), 256);
     if (s.arena_bytes <= s.table_bytes) return LRA_EBUDGET;
-    if (ctx->budget && (size_t)(s.arena_bytes + ctx->dev.bytes) > ctx->budget) return LRA_EBUDGET;
+    if (ctx->budget && (size_t)(s.arena_bytes + ctx->dev_in_use) > ctx->budget) return LRA_EBUDGET;
     if (hipMalloc(&s.arena.p, (size_t)s.arena_bytes) != hipSuccess) {
         s.arena.p = nullptr;
         return LRA_ENOMEM;
     }
     s.arena.bytes = s.arena_bytes;
     ctx->dev_in_use += s.arena_bytes;
+    ctx->dev_allocs += 1;
     s.fl.reset(s.arena_bytes - s.table_bytes);
     s.free_slots.clear();
     for (int i = s.max_active - 1; i >= 0; --i) s.free_slots.push_back(i);
@@ -1751,6 +1816,8 @@ extern "C" lra_status lra_get_stats(lra_ctx* ctx, lra_stats* out)
 {
     if (!ctx || !out) return LRA_EINVAL;
     *out = ctx->stats;
+    out->device_allocs = ctx->dev_allocs;
+    out->device_bytes = ctx->dev_in_use;
     return LRA_OK;
 }
 

@@ -30,7 +30,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 EXPORTS = ["lra_default_options", "lra_create", "lra_destroy", "lra_ca_cur", "lra_maxvol",
            "lra_ca_cur_batched", "lra_submit", "lra_poll", "lra_wait", "lra_serve_config", "lra_set_timing",
            "lra_autotune_team", "lra_autotune_batched", "lra_tuning_save", "lra_tuning_load",
-           "lra_get_stats", "lra_status_str", "lra_version", "lra_ca_cur_noalloc"]
+           "lra_get_stats", "lra_status_str", "lra_version", "lra_ca_cur_noalloc", "lra_cur_factors"]
 
 
 class LraError(RuntimeError):
@@ -68,7 +68,8 @@ class ResultC(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("launches", C.c_int64), ("engine_ms_total", C.c_double),
                 ("last_engine_ms", C.c_double), ("last_grid", C.c_int32),
-                ("last_teams", C.c_int32), ("ticks", C.c_int64)]
+                ("last_teams", C.c_int32), ("ticks", C.c_int64), ("device_allocs", C.c_int64),
+                ("device_bytes", C.c_int64)]
 
 
 class Block(C.Structure):
@@ -104,6 +105,8 @@ def lib():
         L.lra_ca_cur.restype = C.c_int
         L.lra_ca_cur_noalloc.argtypes = L.lra_ca_cur.argtypes
         L.lra_ca_cur_noalloc.restype = C.c_int
+        L.lra_cur_factors.argtypes = [P, C.POINTER(Source), C.c_int64, C.c_int64, C.c_int, P, P, C.c_int32, P, P]
+        L.lra_cur_factors.restype = C.c_int
         L.lra_maxvol.argtypes = [P, P, C.c_int32, C.c_int64, C.c_int64, C.c_int, C.c_double,
                                  C.c_int, P, P, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.lra_maxvol.restype = C.c_int
@@ -376,6 +379,27 @@ class Context:
             res.C = C_t[:kk * src.m].view(kk, src.m).t()       # m x k (column-major)
             res.R = R_t[:kk * src.n].view(kk, src.n)           # k x n (row-major)
         return res
+
+    # -- CUR factors of given index sets ---------------------------------
+    def cur_factors(self, src: DeviceSource, I, J, dtype=None, C_out=None, R_out=None):
+        """lra_cur_factors: C = A[:, J] (returned as an m x k view of a
+        column-major buffer) and R = A[I, :] (k x n), on the device."""
+        import torch
+        I, J = _i64(I), _i64(J)
+        k = len(I)
+        if len(J) != k:
+            raise ValueError("I and J must have the same length")
+        dt = dtype or (torch.float64 if src.struct.dtype == F64 else torch.float32)
+        dev = src.keep[0].device
+        if C_out is None:
+            C_out = torch.empty(k * src.m, dtype=dt, device=dev)
+        if R_out is None:
+            R_out = torch.empty(k * src.n, dtype=dt, device=dev)
+        st = lib().lra_cur_factors(self._h, C.byref(src.struct), src.m, src.n, k, I.ctypes.data, J.ctypes.data,
+                                   F64 if dt == torch.float64 else F32, C_out.data_ptr(), R_out.data_ptr())
+        if st != OK:
+            raise LraError(st, "lra_cur_factors")
+        return C_out.view(k, src.m).t(), R_out.view(k, src.n)
 
     # -- maxvol alone -----------------------------------------------------
     def maxvol(self, strip, tau: float = 0.01, init=None, max_swaps: int = 0):

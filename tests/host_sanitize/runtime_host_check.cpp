@@ -23,6 +23,11 @@ const void* engine_kernel_ptr(int, int)
 }
 hipError_t launch_engine(int, int, int, size_t, bool, const EngineArgs&, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_zero(void*, int64_t, hipStream_t) { return hipErrorNoDevice; }
+hipError_t launch_factors(const DevSource&, int64_t, int64_t, int, const int64_t*, const int64_t*, int, void*, void*,
+                          hipStream_t)
+{
+    return hipErrorNoDevice;
+}
 hipError_t noalloc_scratch_init(int) { return hipErrorNoDevice; }
 void* noalloc_scratch(int) { return nullptr; }
 }  // namespace lra
