@@ -63,7 +63,14 @@ typedef enum {
 
 typedef enum { LRA_SRC_DENSE = 0, LRA_SRC_CAUCHY = 1, LRA_SRC_INVDIST = 2 } lra_src_kind;
 typedef enum { LRA_F32 = 0, LRA_F64 = 1 } lra_dtype;
-typedef enum { LRA_PREC_FP64 = 0, LRA_PREC_MIXED = 1 } lra_prec;
+/* Strip precision.  FP64: strips, basis and swaps in binary64.  MIXED:
+ * strips, basis and swaps in binary32.  BF16SEL: binary32 strips; each
+ * swap's candidates are shortlisted (8 rows per wavefront) from a bfloat16
+ * MFMA product C C[X,:]^{-1} with binary32 accumulation and rechecked in
+ * binary32 before the pivot is chosen (k <= 32, at most 256 strip rows per
+ * workgroup in LDS; other steps use the MIXED selection).  The nucleus and
+ * the residual estimate are binary64 on binary64 entries in every mode. */
+typedef enum { LRA_PREC_FP64 = 0, LRA_PREC_MIXED = 1, LRA_PREC_BF16SEL = 2 } lra_prec;
 
 /* Where the entries a(i,j) come from; the matrix is only ever touched entry
  * by entry (Section 1.1: superfast methods read a tiny fraction of it).
@@ -90,7 +97,7 @@ typedef struct lra_options {
     int32_t k_step;              /* rank increment (8)                                      */
     int32_t max_swaps;           /* swaps per maxvol call; <= 0 means 4k + 64 (0)           */
     int32_t warm_start;          /* 1: each step starts from the previous index set (1)     */
-    int32_t precision;           /* lra_prec: strips/basis in binary64, or binary32 (0)     */
+    int32_t precision;           /* lra_prec: FP64, MIXED or BF16SEL (FP64)                 */
     int32_t sample_q, sample_s;  /* residual sample shape, each 1..64 (64, 64; capped at m, n) */
     int32_t team_wgs;            /* workgroups per problem; 0 = autotuned (0)               */
     int32_t reserved;

@@ -1417,12 +1417,185 @@ NOINL int swap_phase(const TaskDesc& td, Team& tio, int transpose, int keff)
 }
 
 // ----------------------------------------------------------------------------
+// swaps with a BF16 shortlist (binary32 path, k <= 32, one row per thread, the
+// slice in LDS).  The basis is never formed: W = C[X,:]^{-1} (binary32, from
+// the warm-start solve) is kept and updated by the same rank-one formula as
+// B (B = C W, so B - B[:,j] g = C (W - W[:,j] g)).  Each round:
+//   1. the selection product C W on the matrix cores with both operands
+//      rounded to bfloat16 and binary32 accumulation (16x16x32 tiles) into
+//      an LDS copy beside the slice;
+//   2. every row's largest approximate entry, the 8 best rows of each
+//      wavefront (rows of X excluded);
+//   3. those rows' entries recomputed in binary32 (C[i,:] W), their exact
+//      argmax reduced over the workgroup and exchanged over the team with the
+//      winning row as payload; the stop test and the swap use these values.
+// With entrywise error d of the bfloat16 product, the true argmax is on the
+// shortlist whenever it leads the rest by more than 2 d, and at the stop
+// every |C W| entry is at most 1 + tau + 2 d.
+// ----------------------------------------------------------------------------
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+DI uint64_t shfl_xor_u64(uint64_t v, int m)
+{
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <typename T, int KMAX>
+NOINL int swap_phase_bsel(const TaskDesc& td, Team& tio, int transpose, int keff)
+{
+    Team tm = tio;
+    Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
+    int64_t* X = transpose ? sm.J : sm.I;
+    int64_t R;
+    const Rows<T> rw = slice_of<T, KMAX, true>(td, tm, transpose, R);
+    float* Bs = (float*)rw.B + R * KMAX;  // approximate C W, column-major, ld R
+    constexpr int LD = 2 * KMAX;
+    float* Wt = (float*)sm.AUG + KMAX;    // Wt[c * LD + a] = W[a][c]
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double lim = 1.0 + td.tau;
+    const int max_swaps = td.max_swaps > 0 ? td.max_swaps : 4 * keff + 64;
+    const bool has = threadIdx.x < rw.nrows;
+    const int64_t myrow = rw.r0 + threadIdx.x;
+    bool inX = false;
+    for (int c = 0; c < keff; ++c) inX = inX || (X[c] == myrow);
+    const int ntiles = (rw.nrows + 15) / 16;
+    const int ctn = (keff + 15) / 16;
+    int swaps = 0;
+    for (;;) {
+        // 1. selection product in bfloat16, binary32 accumulation
+        for (int tile = wv; tile < ntiles; tile += NWAVE) {
+            const int r = tile * 16 + (lane & 15);
+            const int rc = r < rw.nrows ? r : 0;
+            bf16x8 a;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int d = 8 * (lane >> 4) + j;
+                const float v = rw.B[(d < keff ? d : 0) * rw.ld + rc];
+                a[j] = (__bf16)(d < keff ? v : 0.0f);
+            }
+            for (int ct = 0; ct < ctn; ++ct) {
+                const int c = ct * 16 + (lane & 15);
+                bf16x8 b;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int d = 8 * (lane >> 4) + j;
+                    const float v = Wt[(c < keff ? c : 0) * LD + (d < keff ? d : 0)];
+                    b[j] = (__bf16)((d < keff && c < keff) ? v : 0.0f);
+                }
+                f4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int rr = tile * 16 + 4 * (lane >> 4) + e;
+                    if (rr < rw.nrows && c < keff) Bs[c * R + rr] = acc[e];
+                }
+            }
+        }
+        __syncthreads();
+        // 2. this row's largest approximate entry; the wavefront's 8 best rows
+        K2 key = k2_none();
+        if (has && !inX) {
+            float bv = -1.0f;
+            int bc = 0;
+            for (int c = 0; c < keff; ++c) {
+                const float v = fabsf(Bs[c * R + threadIdx.x]);
+                if (v > bv) {
+                    bv = v;
+                    bc = c;
+                }
+            }
+            key = k2_make((double)bv, myrow, bc);
+        }
+        K2 cand[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            cand[q] = wave_argmax(key);
+            if (key.hi == cand[q].hi && key.lo == cand[q].lo) key = k2_none();
+        }
+        trace_ev(tm, EV_SWAP_RED, 1);
+        // 3. recheck in binary32: lanes 8q .. 8q + 7 take candidate q, columns
+        //    lane % 8 + 8 j
+        const int q = lane >> 3, c0 = lane & 7;
+        K2 mc = cand[0];
+#pragma unroll
+        for (int qq = 1; qq < 8; ++qq)
+            if (qq == q) mc = cand[qq];
+        const bool valid = mc.lo != 0ull;
+        const int lr = valid ? (int)(k2_row(mc) - rw.r0) : 0;
+        constexpr int NJ = (KMAX + 7) / 8;
+        float ex[NJ];
+        K2 best = k2_none();
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int c = c0 + 8 * j;
+            const int cc = c < keff ? c : 0;
+            float acc = 0.0f;
+            for (int a = 0; a < keff; ++a) acc = fmaf(rw.B[a * rw.ld + lr], Wt[cc * LD + a], acc);
+            ex[j] = acc;
+            if (valid && c < keff) {
+                const K2 kk = k2_make(fabs((double)acc), k2_row(mc), c);
+                if (k2_better(kk, best)) best = kk;
+            }
+        }
+#pragma unroll
+        for (int o = 4; o >= 1; o >>= 1) {
+            const K2 other{shfl_xor_u64(best.hi, o), shfl_xor_u64(best.lo, o)};
+            if (k2_better(other, best)) best = other;
+        }
+        const K2 gb = block_argmax(best, sm, tm);
+        if (valid && gb.lo != 0ull && k2_row(mc) == k2_row(gb)) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int c = c0 + 8 * j;
+                if (c < keff) sm.pay[c] = ex[j];
+            }
+        }
+        __syncthreads();
+        const K2 wv2 = team_argmax(tm, sm, gb, keff, R);
+        if (tm.failed) {
+            tio = tm;
+            return -1;
+        }
+        trace_ev(tm, EV_SWAP_XCH, 1);
+        if (!(k2_val(wv2) > lim)) break;
+        if (swaps == max_swaps) {
+            if (threadIdx.x == 0) sm.warn |= W_CAP;
+            break;
+        }
+        const int js = k2_col(wv2);
+        const int64_t is = k2_row(wv2);
+        const int64_t was = X[js];
+        if (threadIdx.x < keff) {
+            sm.g[threadIdx.x] = (sm.pay[threadIdx.x] - (T)(threadIdx.x == js ? 1 : 0)) / sm.pay[js];
+            sm.lumul[0][threadIdx.x] = Wt[js * LD + threadIdx.x];  // W[:, js]
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) X[js] = is;
+        for (int e = threadIdx.x; e < keff * keff; e += NT) {
+            const int c = e / keff, a = e % keff;
+            Wt[c * LD + a] -= (float)sm.lumul[0][a] * sm.g[c];
+        }
+        inX = has && (myrow == is || (inX && myrow != was));
+        ++swaps;
+        trace_ev(tm, EV_SWAP, swaps);
+        __syncthreads();
+    }
+    trace_ev(tm, EV_STEP_END, swaps);
+    __syncthreads();
+    tio = tm;
+    return swaps;
+}
+
+// ----------------------------------------------------------------------------
 // one maxvol step (Section 6.5): column step (transpose = 0) picks I from
 // A[:, J]; row step (transpose = 1) picks J from A[I, :]^T.
 // ----------------------------------------------------------------------------
 
 template <typename T, int KMAX, bool LDSB>
-DI void maxvol_step(const TaskDesc& td, Team& tm, int transpose)
+DI void maxvol_step(const TaskDesc& td, Team& tm, int transpose, int lds_b_bytes)
 {
     Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
     const int k = sm.k;
@@ -1430,6 +1603,13 @@ DI void maxvol_step(const TaskDesc& td, Team& tm, int transpose)
     const bool have_X = transpose ? true : (sm.have_I != 0);
     const bool warm = have_X && td.warm_start;
     const double u = sizeof(T) == 8 ? 0x1p-53 : 0x1p-24;
+    // the BF16 shortlist needs one row per thread and room for the
+    // approximate product beside the slice in LDS
+    bool bsel = false;
+    if constexpr (std::is_same<T, float>::value && KMAX <= 32 && LDSB) {
+        const int64_t R = (M + tm.size - 1) / tm.size;
+        bsel = td.bf16_select != 0 && R <= NT && R * KMAX * 2 * (int64_t)sizeof(T) <= lds_b_bytes;
+    }
     trace_ev(tm, EV_STEP_BEGIN, transpose);
 
     const double cmax = gather_phase<T, KMAX, LDSB>(td, tm, transpose, warm ? 1 : 0);
@@ -1445,14 +1625,37 @@ DI void maxvol_step(const TaskDesc& td, Team& tm, int transpose)
     const double thresh = 64.0 * u * cmax;
     trace_ev(tm, EV_GATHERED, 0);
 
-    const int started = warm_ok && minpiv > thresh;
+    int started = warm_ok && minpiv > thresh;
     int keff = k;
     if (!started) {
         keff = gepp_phase<T, KMAX, LDSB>(td, tm, transpose, thresh);
         if (keff < 0) return;
+        if (bsel && keff == k) {
+            // the shortlist works from C and C[X,:]^{-1}: gather the strip
+            // again and solve with the LU start's rows, as a warm start
+            gather_phase<T, KMAX, LDSB>(td, tm, transpose, 1);
+            if (tm.failed) return;
+            if (threadIdx.x == 0) sm.entries_read += M * k;
+            started = sm.ok && sm.minpiv > thresh;
+            if (!started) {
+                keff = gepp_phase<T, KMAX, LDSB>(td, tm, transpose, thresh);
+                if (keff < 0) return;
+            }
+        }
+        bsel = bsel && started;
     }
-    basis_phase<T, KMAX, LDSB>(td, tm, transpose, started, keff);
-    const int swaps = swap_phase<T, KMAX, LDSB>(td, tm, transpose, keff);
+    int swaps;
+    if constexpr (std::is_same<T, float>::value && KMAX <= 32 && LDSB) {
+        if (bsel) {
+            swaps = swap_phase_bsel<T, KMAX>(td, tm, transpose, keff);
+        } else {
+            basis_phase<T, KMAX, LDSB>(td, tm, transpose, started, keff);
+            swaps = swap_phase<T, KMAX, LDSB>(td, tm, transpose, keff);
+        }
+    } else {
+        basis_phase<T, KMAX, LDSB>(td, tm, transpose, started, keff);
+        swaps = swap_phase<T, KMAX, LDSB>(td, tm, transpose, keff);
+    }
     if (swaps < 0) return;
     if (threadIdx.x == 0) {
         sm.swaps_total += swaps;
@@ -1473,8 +1676,8 @@ DI void maxvol_dispatch(const TaskDesc& td, Team& tm, int transpose, int lds_b_b
     const int64_t M = transpose ? td.n : td.m;
     const int64_t R = (M + tm.size - 1) / tm.size;
     trace_ev(tm, EV_DISPATCH, transpose);
-    if (R * sm.k * (int64_t)sizeof(T) <= lds_b_bytes) maxvol_step<T, KMAX, true>(td, tm, transpose);
-    else maxvol_step<T, KMAX, false>(td, tm, transpose);
+    if (R * sm.k * (int64_t)sizeof(T) <= lds_b_bytes) maxvol_step<T, KMAX, true>(td, tm, transpose, lds_b_bytes);
+    else maxvol_step<T, KMAX, false>(td, tm, transpose, lds_b_bytes);
 }
 
 // ----------------------------------------------------------------------------
@@ -1990,13 +2193,13 @@ NOINL void reduce_leader(const TaskDesc& td, Team& tio, int lds_b_bytes)
             sm.prevJ[threadIdx.x] = sm.J[threadIdx.x];
         }
         __syncthreads();
-        if (lds) maxvol_step<T, KMAX, true>(sub, one, 0);
-        else maxvol_step<T, KMAX, false>(sub, one, 0);
+        if (lds) maxvol_step<T, KMAX, true>(sub, one, 0, lds_b_bytes);
+        else maxvol_step<T, KMAX, false>(sub, one, 0, lds_b_bytes);
         if (sm.phase == PH_DONE) break;
         if (threadIdx.x == 0) sm.have_I = 1;
         __syncthreads();
-        if (lds) maxvol_step<T, KMAX, true>(sub, one, 1);
-        else maxvol_step<T, KMAX, false>(sub, one, 1);
+        if (lds) maxvol_step<T, KMAX, true>(sub, one, 1, lds_b_bytes);
+        else maxvol_step<T, KMAX, false>(sub, one, 1, lds_b_bytes);
         if (sm.phase == PH_DONE) break;
         if (had && sm.k == k_before) {
             if (threadIdx.x == 0) {

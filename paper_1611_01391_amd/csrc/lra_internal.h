@@ -69,6 +69,8 @@ struct TaskDesc {
     int32_t cur_rank;      // Cynical reduction to this rank after the sweeps (0: none)
     int32_t inner_sweeps;  // C-A sweeps of the reduction inside the k x k block
     int32_t nucleus_rank;  // truncated pseudo-inverse nucleus of this rank (0: inverse)
+    int32_t bf16_select;   // binary32 path: BF16 shortlist + binary32 recheck in the swaps
+    int32_t pad_t;
 };
 
 constexpr int NVARIANT = 8;

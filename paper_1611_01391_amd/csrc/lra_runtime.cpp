@@ -315,6 +315,7 @@ struct Prob {
     bool have_init_I = false;
     std::vector<int64_t> init_I;
     int cur_rank = 0, inner_sweeps = 4, nucleus_rank = 0;
+    int bf16_select = 0;
 };
 
 static lra_status make_prob(const lra_source* src, int64_t m, int64_t n, int k, int sweeps, double tol,
@@ -329,7 +330,8 @@ static lra_status make_prob(const lra_source* src, int64_t m, int64_t n, int k, 
     if (o->cur_rank > 0 && o->cur_rank < k && o->inner_sweeps < 1) return LRA_EINVAL;
     if (!(o->tau >= 0.0) || o->k_step < 1 || o->k_max > 64) return LRA_EINVAL;
     if (src->kind == LRA_SRC_DENSE && src->lda < (src->col_major ? m : n)) return LRA_EINVAL;
-    if (o->precision != LRA_PREC_FP64 && o->precision != LRA_PREC_MIXED) return LRA_EINVAL;
+    if (o->precision != LRA_PREC_FP64 && o->precision != LRA_PREC_MIXED && o->precision != LRA_PREC_BF16SEL)
+        return LRA_EINVAL;
     p.src.kind = src->kind;
     p.src.dtype = src->dtype;
     p.src.a = src->a;
@@ -382,6 +384,7 @@ static lra_status make_prob(const lra_source* src, int64_t m, int64_t n, int k, 
         if (v < 0 || v >= m) return LRA_EINVAL;
     for (int64_t v : p.S)
         if (v < 0 || v >= n) return LRA_EINVAL;
+    p.bf16_select = o->precision == LRA_PREC_BF16SEL ? 1 : 0;
     p.cur_rank = o->cur_rank < k ? o->cur_rank : 0;
     p.inner_sweeps = o->inner_sweeps;
     p.nucleus_rank = o->nucleus_rank < k ? o->nucleus_rank : 0;
@@ -503,6 +506,8 @@ static void fill_task(TaskDesc& td, const Prob& p, uint8_t* base, const ProbRegi
     td.cur_rank = p.cur_rank;
     td.inner_sweeps = p.inner_sweeps;
     td.nucleus_rank = p.nucleus_rank;
+    td.bf16_select = p.bf16_select;
+    td.pad_t = 0;
 }
 
 // Host image of the inputs (cand, Q, S) and of the initial state (st, I, J).

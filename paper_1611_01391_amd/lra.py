@@ -24,7 +24,7 @@ EINVAL, ERANK, ENOMEM, EBUDGET, EDEVICE, ENONFINITE, ESCRATCH = -1, -2, -3, -4, 
 NOALLOC_SCRATCH_BYTES = 64 << 20
 SRC_DENSE, SRC_CAUCHY, SRC_INVDIST = 0, 1, 2
 F32, F64 = 0, 1
-PREC_FP64, PREC_MIXED = 0, 1
+PREC_FP64, PREC_MIXED, PREC_BF16SEL = 0, 1, 2
 
 # every entry point declared in include/lra.h
 EXPORTS = ["lra_default_options", "lra_create", "lra_destroy", "lra_ca_cur", "lra_maxvol",
