@@ -36,7 +36,8 @@ def build(force: bool = True) -> str:
 class Source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("a", C.c_void_p),
                 ("lda", C.c_int64), ("col_major", C.c_int32), ("pad_", C.c_int32),
-                ("x", C.c_void_p), ("y", C.c_void_p)]
+                ("x", C.c_void_p), ("y", C.c_void_p), ("depth", C.c_int32), ("pad2_", C.c_int32),
+                ("seed", C.c_uint64), ("pm", C.c_int64), ("pn", C.c_int64)]
 
 
 class Trace(C.Structure):
@@ -148,6 +149,22 @@ def dense(a: np.ndarray, col_major: bool = False) -> HostSource:
         lda = a.shape[1]
     s = Source(0, dt, _ptr(arr), lda, 1 if col_major else 0, 0, None, None)
     return HostSource(0, dt, (arr,), s, a.shape[0], a.shape[1])
+
+
+def abridged(a: np.ndarray, depth: int, seed: int, col_major: bool = False) -> HostSource:
+    """F A H: the dense matrix pre-processed by d-abridged Hadamard multipliers
+    with random sign scaling on both sides (orthogonal F and H)."""
+    src = dense(a, col_major)
+    m, n = a.shape
+    if depth < 1 or m % (1 << depth) or n % (1 << depth):
+        raise ValueError("2^depth must divide both dimensions")
+    src.struct.kind = 3
+    src.struct.depth = depth
+    src.struct.seed = seed & 0xFFFFFFFFFFFFFFFF
+    src.struct.pm = m
+    src.struct.pn = n
+    src.kind = 3
+    return src
 
 
 def cauchy(x: np.ndarray, y: np.ndarray) -> HostSource:

@@ -26,9 +26,33 @@ static double load_pt(const void* p, int dtype, int64_t i)
     return dtype == 0 ? (double)((const float*)p)[i] : ((const double*)p)[i];
 }
 
+/* +-1 of value number idx of SplitMix64 stream `seed` (its top bit). */
+static double pre_sign(uint64_t seed, int64_t idx)
+{
+    return (oracle_splitmix64(seed, (uint64_t)idx) >> 63) ? -1.0 : 1.0;
+}
+
+/* (F A H)_ij of the abridged scaled Hadamard pre-processing (oracle.h). */
+static double preprocessed(const oracle_source* s, int64_t i, int64_t j)
+{
+    const int d = s->depth;
+    const int64_t bm = s->pm >> d, bn = s->pn >> d;
+    const int64_t ib = i / bm, ir = i % bm, jb = j / bn, jr = j % bn;
+    double acc = 0.0;
+    for (int64_t t = 0; t < ((int64_t)1 << d); ++t)
+        for (int64_t u = 0; u < ((int64_t)1 << d); ++u) {
+            const double v = load_dense(s, ir + t * bm, jr + u * bn);
+            const int neg = (__builtin_popcountll((unsigned long long)(ib & t)) +
+                             __builtin_popcountll((unsigned long long)(u & jb))) & 1;
+            acc += neg ? -v : v;
+        }
+    return acc * pre_sign(s->seed, i) * pre_sign(s->seed + 1, j) * ldexp(1.0, -d);
+}
+
 double oracle_entry_f64(const oracle_source* s, int64_t i, int64_t j)
 {
     if (s->kind == 0) return load_dense(s, i, j);
+    if (s->kind == 3) return preprocessed(s, i, j);
     double d = load_pt(s->x, s->dtype, i) - load_pt(s->y, s->dtype, j);
     if (s->kind == 1) return 1.0 / d;
     d = fabs(d);
@@ -37,6 +61,7 @@ double oracle_entry_f64(const oracle_source* s, int64_t i, int64_t j)
 
 float oracle_entry_f32(const oracle_source* s, int64_t i, int64_t j)
 {
+    if (s->kind == 3) return (float)preprocessed(s, i, j);
     if (s->kind == 0) {
         int64_t off = s->col_major ? j * s->lda + i : i * s->lda + j;
         return s->dtype == 0 ? ((const float*)s->a)[off] : (float)((const double*)s->a)[off];

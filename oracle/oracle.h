@@ -41,9 +41,13 @@ extern "C" {
 #endif
 
 /* Entry source (host pointers). kind: 0 dense, 1 Cauchy 1/(x_i - y_j),
- * 2 inverse distance 1/|x_i - y_j| (0 where x_i == y_j).
+ * 2 inverse distance 1/|x_i - y_j| (0 where x_i == y_j), 3 the dense matrix
+ * pre-processed by abridged scaled Hadamard multipliers (see
+ * oracle_entry_f64).
  * dtype: 0 = float32, 1 = float64 (element type of a, or of x and y).
- * Dense: element (i,j) at a[i*lda + j] (row-major) or a[j*lda + i]. */
+ * Dense: element (i,j) at a[i*lda + j] (row-major) or a[j*lda + i].
+ * Kind 3 also uses depth d (1 <= d, 2^d dividing pm and pn), the sign seed
+ * and the dimensions pm x pn of a. */
 typedef struct {
     int32_t kind;
     int32_t dtype;
@@ -53,6 +57,10 @@ typedef struct {
     int32_t pad_;
     const void* x;
     const void* y;
+    int32_t depth;
+    int32_t pad2_;
+    uint64_t seed;
+    int64_t pm, pn;
 } oracle_source;
 
 /* Smallest recorded decision margins of one run (relative). */
@@ -86,7 +94,16 @@ typedef struct {
     oracle_trace trace;
 } oracle_result;
 
-/* entry a(i,j) in binary64 (nucleus and residual precision). */
+/* entry a(i,j) in binary64 (nucleus and residual precision).
+ * Kind 3 (Section 8.3, family (i): d-abridged Hadamard multipliers with
+ * random diagonal scaling, applied on both sides as in Section 6.6):
+ * a(i,j) = (F A H)_ij with F = D_F H_{pm,d} / 2^{d/2}, H = H_{pn,d} D_H / 2^{d/2},
+ * H_{n,d} = H_{2^d} (Sylvester, entry (a,b) = (-1)^{popcount(a & b)})
+ * Kronecker I_{n/2^d}, D_F = diag(+-1) from SplitMix64 stream seed (top bit of
+ * value i), D_H from stream seed + 1.  F and H are orthogonal.  The sum runs
+ * over the 2^d x 2^d entries A[i mod s + t s, j mod s' + u s'] (s = pm/2^d,
+ * s' = pn/2^d), t outer, u inner, in binary64, then times the signs and 2^-d
+ * (exact). */
 double oracle_entry_f64(const oracle_source* src, int64_t i, int64_t j);
 /* entry a(i,j) as it enters a binary32 strip. */
 float oracle_entry_f32(const oracle_source* src, int64_t i, int64_t j);
