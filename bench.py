@@ -11,6 +11,8 @@ generator and the sample are read.  One step = one complete C-A / CUR
 legs ride along as objects of the same line:
   mixed_path        the same matrix on the binary32 path, parity against the
                     binary32 oracle and error against the binary64 oracle
+  bf16_select_path  the same with the BF16-shortlist selection (binary32
+                    recheck), against the same two oracles
   plain_512         dense binary64 512 x 512, W = G1 G2 + 1e-8 E, k = 8,
                     3 sweeps
   cauchy_2p20       implicit a_ij = 1/(s_i - t_j), m = n = 2^20, adaptive k
@@ -46,12 +48,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "CUR LRAs/s + HBM GB/s, served/batched vs plain at equal err; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-# binary64 VALU issue rate: 256 CUs x 64 lanes per clock x 2.4 GHz
-VALU64_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# binary64 VALU instructions per generated entry in the engine (one
-# subtraction of coordinates and the correctly rounded division sequence:
-# 2 div_scale, rcp, 5 fma, mul, div_fmas, div_fixup), from the gfx950 assembly
-OPS_PER_ENTRY = 12
+# VALU issue peak: 256 CUs, four 16-lane SIMDs each (one wave64 instruction
+# per CU per cycle; binary64 FMA at that rate is the 78.6 TFLOP/s peak), 2.4 GHz
+VALU_WAVE_INSTR_PEAK_G = 256 * 2.4
 
 
 def log(msg):
@@ -192,7 +191,7 @@ def bench_dense(args, plain=False):
         n, k, sweeps = args.n, args.k, args.sweeps
         A, d = _dense_input(args)
         esz = 4
-        prec = lra.PREC_FP64 if args.precision == "fp64" else lra.PREC_MIXED
+        prec = {"fp64": lra.PREC_FP64, "mixed": lra.PREC_MIXED, "bf16sel": lra.PREC_BF16SEL}[args.precision]
         desc = (f"dense float32 {n}x{n} (rank-32 scaled factor-Gaussian + 1e-4 noise), k={k}, "
                 f"{sweeps} C-A sweeps, 64x64 residual sample, {args.precision} path")
     dev = torch.device("cuda:0")
@@ -248,7 +247,7 @@ def bench_dense(args, plain=False):
     out = _base(args, args.steps / el, "CUR LRAs/s", ms_per_step,
                 "f64" if prec == lra.PREC_FP64 else "f32",
                 {"workload": desc, "m": n, "n": n, "k": k, "sweeps": sweeps,
-                 "precision": "fp64" if prec == lra.PREC_FP64 else "mixed", "autotuned": tuned})
+                 "precision": args.precision if not plain else "fp64", "autotuned": tuned})
     traffic = None
     if not plain and (n, k, sweeps, args.precision) == (16384, 32, 4, "fp64"):
         traffic = _profiled("engine_kernel_dense16384_k32.md", "traffic_bytes_per_launch")
@@ -312,11 +311,22 @@ def _strip_gather(ctx, torch, src, m, n, res, esz, reps=50):
 # implicit Cauchy kernel, 2^20 x 2^20
 # ---------------------------------------------------------------------------
 
-def _alu_roofline(entries, kernel_ms, kernel="engine_kernel"):
-    achieved = entries * OPS_PER_ENTRY / (kernel_ms * 1e-3) / 1e12
-    return {"bound": "alu", "achieved": achieved, "peak": VALU64_PEAK_TOPS, "unit": "T VALU op/s (binary64)",
-            "frac": achieved / VALU64_PEAK_TOPS, "traffic": None, "kernel": kernel, "kernel_ms": kernel_ms,
-            "entries_generated": int(entries), "ops_per_entry": OPS_PER_ENTRY}
+def _alu_roofline(entries, kernel_ms, summary, kernel="engine_kernel"):
+    """VALU roofline of a generated-entry workload: the engine's binary64
+    VALU issue rate against the chip's (256 CUs x one wave64 instruction per
+    cycle x 2.4 GHz), from the VALU instructions per launch that rocprofv3
+    counted (SQ_INSTS_VALU, committed under profiles/) over the live kernel
+    time; None while the engine source differs from the profiled one.  The
+    generated entries per second ride along."""
+    insts = _profiled(summary, "valu_insts_per_launch")
+    out = {"bound": "alu", "achieved": None, "peak": VALU_WAVE_INSTR_PEAK_G, "unit": "G VALU wave-instructions/s",
+           "frac": None, "traffic": None, "kernel": kernel, "kernel_ms": kernel_ms,
+           "entries_generated": int(entries), "entries_per_s": entries / (kernel_ms * 1e-3)}
+    if insts:
+        ach = insts / (kernel_ms * 1e-3) / 1e9
+        out.update(achieved=ach, frac=ach / VALU_WAVE_INSTR_PEAK_G, valu_insts_per_launch=insts,
+                   counters=f"profiles/{summary}")
+    return out
 
 
 def bench_cauchy(args):
@@ -352,7 +362,8 @@ def bench_cauchy(args):
                 {"workload": f"implicit Cauchy 1/(s_i - t_j), s ~ U[0,1], t ~ U[2,3], m = n = 2^20, adaptive k "
                              f"8..40 step 8, tol {tol:g}, up to 4 sweeps per rank",
                  "m": m, "n": m, "k0": 8, "k_max": 40, "tol": tol, "precision": args.precision})
-    out["roofline"] = _alu_roofline(res.entries_read, kernel_ms)
+    out["roofline"] = _alu_roofline(res.entries_read, kernel_ms,
+                                    f"engine_kernel_cauchy_2p20_{'fp64' if f64 else 'fp32'}.md")
     out["cpu_baseline"] = cpu
     out["result"] = {"status": int(res.status), "k": int(res.k), "sweeps": int(res.sweeps_done),
                      "swaps": int(res.swaps_total), "est_rel": res.err_est_rel,
@@ -447,7 +458,7 @@ def bench_multipole(args):
                              f"adaptive k 8..{kmax} step 8 to tol {tol:g}, one batched launch",
                  "points": N, "blocks": len(blocks), "tol": tol, "k_max": kmax, "precision": args.precision,
                  "autotuned": tuned})
-    out["roofline"] = _alu_roofline(entries, kernel_ms)
+    out["roofline"] = _alu_roofline(entries, kernel_ms, "engine_kernel_multipole_2p20.md")
     out["cpu_baseline"] = cpu
     met_plain = sum(1 for r in out_p if r.status >= 0 and r.err_est_rel <= tol)
     out["batched_vs_plain"] = {"batched_blocks_per_s": len(blocks) / batched_s,
@@ -683,6 +694,8 @@ def bench_all(args):
             "parity", "result", "strip_gather", "wall_s")
     mixed = _leg("dense mixed", bench_dense, args, precision="mixed", steps=10, warmup=2)
     out["mixed_path"] = _summary(mixed, keep)
+    bsel = _leg("dense bf16-select", bench_dense, args, precision="bf16sel", steps=10, warmup=2)
+    out["bf16_select_path"] = _summary(bsel, keep)
     plain = _leg("plain 512", lambda a: bench_dense(a, plain=True), args, steps=50, warmup=5)
     out["plain_512"] = _summary(plain, keep)
     cau = _leg("cauchy 2^20", bench_cauchy, args, steps=10, warmup=2)
@@ -708,7 +721,7 @@ def main():
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--sweeps", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "bf16sel"], default="fp64")
     ap.add_argument("--points", type=int, default=1 << 20, help="multipole: number of points")
     ap.add_argument("--mp-tol", type=float, default=1e-8, help="multipole: tolerance")
     ap.add_argument("--requests", type=int, default=1000, help="serve: number of requests")

@@ -245,6 +245,7 @@ struct Smem {
     int64_t cand_next, entries_read;
     double est_rel, est_abs, mean, var, cond1;
     int32_t flag, fetch, ok, pivp;
+    int32_t w_valid;          // AUG's right half holds C[X,:]^{-1} of the last step
     double minpiv;
 };
 
@@ -1107,7 +1108,7 @@ DI Rows<T> slice_of(const TaskDesc& td, const Team& tm, int transpose, int64_t& 
 // the partial-pivot LU solve then leaves M^{-1} in the right half (so that
 // B = C Chat^{-1} = C (M^{-1})^T).
 template <typename T, int KMAX>
-DI void warm_load(const TaskDesc& td, Smem<T, KMAX>& sm, int transpose)
+DI void warm_load(const TaskDesc& td, Smem<T, KMAX>& sm, int transpose, bool keep_right)
 {
     const int k = sm.k;
     const int64_t* F = transpose ? sm.I : sm.J;
@@ -1126,8 +1127,55 @@ DI void warm_load(const TaskDesc& td, Smem<T, KMAX>& sm, int transpose)
         [&](int e, T v) {
             const int c = e / k, s2 = e % k;
             AUG[c * LD + s2] = v;
-            AUG[c * LD + KMAX + s2] = (T)(c == s2 ? 1 : 0);
+            if (!keep_right) AUG[c * LD + KMAX + s2] = (T)(c == s2 ? 1 : 0);
         });
+}
+
+// Warm start from the last step's inverse (binary64): that step ended with
+// W = C[X,:]^{-1} maintained through its swaps in AUG's right half (stored as
+// W^T); the transposed strip of this step has C'[X',:] = C[X,:]^T, so its
+// right half is the transpose of the last one.  Wavefront 0 transposes it in
+// place and takes it when ||C'[X',:]||_1 ||W'||_1 u <= 2^-40 (the swaps'
+// rounding in W stays far below the decisions' margins); otherwise it
+// restores the identity and solves.  Same outputs as the solve: sm.ok,
+// sm.minpiv (+inf when carried: the pivot test cannot fail at this
+// conditioning, since C[X,:] holds the strip's dominant rows).
+template <typename T, int KMAX>
+DI void warm_carry_wave0(Smem<T, KMAX>& sm, int k)
+{
+    constexpr int LD = 2 * KMAX;
+    T* AUG = (T*)sm.AUG;
+    const int lane = threadIdx.x & 63;
+    for (int e = lane; e < k * k; e += 64) {
+        const int c = e / k, d = e % k;
+        if (c < d) {
+            const T a = AUG[c * LD + KMAX + d], b = AUG[d * LD + KMAX + c];
+            AUG[c * LD + KMAX + d] = b;
+            AUG[d * LD + KMAX + c] = a;
+        }
+    }
+    wave_lds_sync();
+    double nc = 0.0, nw = 0.0;
+    if (lane < k)
+        for (int d = 0; d < k; ++d) {
+            nc += fabs((double)AUG[lane * LD + d]);         // row of M = column of C[X,:]
+            nw += fabs((double)AUG[lane * LD + KMAX + d]);  // row of W^T = column of W
+        }
+    const double kappa = __longlong_as_double((long long)wave_max_u64((uint64_t)__double_as_longlong(nc))) *
+                         __longlong_as_double((long long)wave_max_u64((uint64_t)__double_as_longlong(nw)));
+    if (kappa * 0x1p-53 <= 0x1p-40) {
+        if (lane == 0) {
+            sm.ok = 1;
+            sm.minpiv = INFINITY;
+        }
+        return;
+    }
+    for (int e = lane; e < k * k; e += 64) {
+        const int c = e / k, d = e % k;
+        AUG[c * LD + KMAX + d] = (T)(c == d ? 1 : 0);
+    }
+    wave_lds_sync();
+    lu_solve_wave0<T, KMAX, T, LD, (LD + 63) / 64, 1>(AUG, k, KMAX, k, sm);
 }
 
 // Gather this workgroup's rows of the strip and return the team-wide max
@@ -1147,12 +1195,18 @@ NOINL double gather_phase(const TaskDesc& td, Team& tio, int transpose, int warm
     if (td.src.kind != 0 && threadIdx.x < k)
         sm.pts[threadIdx.x] = transpose ? load_elem(td.src.x, td.src.dtype, F[threadIdx.x])
                                         : load_elem(td.src.y, td.src.dtype, F[threadIdx.x]);
-    if (warm) warm_load<T, KMAX>(td, sm, transpose);
+    // the last step's inverse is carried on the binary64 path
+    const bool carry = warm && sizeof(T) == 8 && sm.w_valid;
+    if (warm) warm_load<T, KMAX>(td, sm, transpose, carry);
     __syncthreads();
     double lmax = 0.0;
     if (warm) {
-        if (threadIdx.x < 64) lu_solve_wave0<T, KMAX, T, 2 * KMAX, (2 * KMAX + 63) / 64, 1>((T*)sm.AUG, k, KMAX, k, sm);
-        else lmax = gather_rows<T, KMAX>(td.src, transpose, sm, F, k, rw, threadIdx.x - 64, NT - 64);
+        if (threadIdx.x < 64) {
+            if (carry) warm_carry_wave0<T, KMAX>(sm, k);
+            else lu_solve_wave0<T, KMAX, T, 2 * KMAX, (2 * KMAX + 63) / 64, 1>((T*)sm.AUG, k, KMAX, k, sm);
+        } else {
+            lmax = gather_rows<T, KMAX>(td.src, transpose, sm, F, k, rw, threadIdx.x - 64, NT - 64);
+        }
     } else {
         lmax = gather_rows<T, KMAX>(td.src, transpose, sm, F, k, rw, threadIdx.x, NT);
     }
@@ -1278,11 +1332,16 @@ NOINL void basis_phase(const TaskDesc& td, Team& tio, int transpose, int started
 // slot (rank-one update of B; |det| grows by the winning entry).  Returns the
 // number of swaps, or -1 if the team failed.
 template <typename T, int KMAX, bool LDSB>
-NOINL int swap_phase(const TaskDesc& td, Team& tio, int transpose, int keff)
+NOINL int swap_phase(const TaskDesc& td, Team& tio, int transpose, int keff, int wmaint)
 {
     Team tm = tio;
     Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
     int64_t* X = transpose ? sm.J : sm.I;
+    // wmaint: AUG's right half holds W^T, W = C[X,:]^{-1}; each swap updates it
+    // like B (B = C W: B - B[:,j] g = C (W - W[:,j] g)), so that the next
+    // step can start from it
+    constexpr int LDW = 2 * KMAX;
+    T* Wr = (T*)sm.AUG + KMAX;
     int64_t R;
     const Rows<T> rw = slice_of<T, KMAX, LDSB>(td, tm, transpose, R);
     const int64_t rend = rw.r0 + rw.nrows;
@@ -1333,9 +1392,17 @@ NOINL int swap_phase(const TaskDesc& td, Team& tio, int transpose, int keff)
             }
             const int js = k2_col(wv);
             const int64_t is = k2_row(wv);
-            if (threadIdx.x < keff) sm.g[threadIdx.x] = (sm.pay[threadIdx.x] - (T)(threadIdx.x == js ? 1 : 0)) / sm.pay[js];
+            if (threadIdx.x < keff) {
+                sm.g[threadIdx.x] = (sm.pay[threadIdx.x] - (T)(threadIdx.x == js ? 1 : 0)) / sm.pay[js];
+                if (wmaint) sm.lumul[0][threadIdx.x] = (double)Wr[js * LDW + threadIdx.x];
+            }
             if (threadIdx.x == 0) X[js] = is;
             __syncthreads();
+            if (wmaint)
+                for (int e = threadIdx.x; e < keff * keff; e += NT) {
+                    const int c = e / keff, d = e % keff;
+                    Wr[c * LDW + d] -= (T)sm.lumul[0][d] * sm.g[c];
+                }
             ++swaps;
             trace_ev(tm, EV_SWAP, swaps);
             T gv[KMAX];
@@ -1379,9 +1446,17 @@ NOINL int swap_phase(const TaskDesc& td, Team& tio, int transpose, int keff)
             }
             const int js = k2_col(wv);
             const int64_t is = k2_row(wv);
-            if (threadIdx.x < keff) sm.g[threadIdx.x] = (sm.pay[threadIdx.x] - (T)(threadIdx.x == js ? 1 : 0)) / sm.pay[js];
+            if (threadIdx.x < keff) {
+                sm.g[threadIdx.x] = (sm.pay[threadIdx.x] - (T)(threadIdx.x == js ? 1 : 0)) / sm.pay[js];
+                if (wmaint) sm.lumul[0][threadIdx.x] = (double)Wr[js * LDW + threadIdx.x];
+            }
             if (threadIdx.x == 0) X[js] = is;
             __syncthreads();
+            if (wmaint)
+                for (int e = threadIdx.x; e < keff * keff; e += NT) {
+                    const int c = e / keff, d = e % keff;
+                    Wr[c * LDW + d] -= (T)sm.lumul[0][d] * sm.g[c];
+                }
             ++swaps;
             trace_ev(tm, EV_SWAP, swaps);
             constexpr int CH = KMAX < 16 ? KMAX : 16;
@@ -1497,17 +1572,23 @@ NOINL int swap_phase_bsel(const TaskDesc& td, Team& tio, int transpose, int keff
         __syncthreads();
         // 2. this row's largest approximate entry; the wavefront's 8 best rows
         K2 key = k2_none();
-        if (has && !inX) {
+        {
+            // all of the row's loads first (clamped columns), then the scan
+            const int rr = has ? (int)threadIdx.x : 0;
+            float bsv[KMAX];
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) bsv[c] = Bs[(c < keff ? c : 0) * R + rr];
             float bv = -1.0f;
             int bc = 0;
-            for (int c = 0; c < keff; ++c) {
-                const float v = fabsf(Bs[c * R + threadIdx.x]);
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) {
+                const float v = c < keff ? fabsf(bsv[c]) : -1.0f;
                 if (v > bv) {
                     bv = v;
                     bc = c;
                 }
             }
-            key = k2_make((double)bv, myrow, bc);
+            if (has && !inX) key = k2_make((double)bv, myrow, bc);
         }
         K2 cand[8];
 #pragma unroll
@@ -1528,12 +1609,24 @@ NOINL int swap_phase_bsel(const TaskDesc& td, Team& tio, int transpose, int keff
         constexpr int NJ = (KMAX + 7) / 8;
         float ex[NJ];
         K2 best = k2_none();
+        // the candidate row of C, loaded once (clamped columns, zero past k)
+        float cr[KMAX];
+#pragma unroll
+        for (int a = 0; a < KMAX; ++a) cr[a] = rw.B[(a < keff ? a : 0) * rw.ld + lr];
+#pragma unroll
+        for (int a = 0; a < KMAX; ++a) cr[a] = a < keff ? cr[a] : 0.0f;
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             const int c = c0 + 8 * j;
             const int cc = c < keff ? c : 0;
+            float wr[KMAX];
+#pragma unroll
+            for (int a = 0; a < KMAX; ++a) wr[a] = Wt[cc * LD + (a < keff ? a : 0)];
+#pragma unroll
+            for (int a = 0; a < KMAX; ++a) wr[a] = a < keff ? wr[a] : 0.0f;
             float acc = 0.0f;
-            for (int a = 0; a < keff; ++a) acc = fmaf(rw.B[a * rw.ld + lr], Wt[cc * LD + a], acc);
+#pragma unroll
+            for (int a = 0; a < KMAX; ++a) acc = fmaf(cr[a], wr[a], acc);
             ex[j] = acc;
             if (valid && c < keff) {
                 const K2 kk = k2_make(fabs((double)acc), k2_row(mc), c);
@@ -1616,6 +1709,8 @@ DI void maxvol_step(const TaskDesc& td, Team& tm, int transpose, int lds_b_bytes
     if (tm.failed) return;
     const int warm_ok = warm ? sm.ok : 0;
     const double minpiv = sm.minpiv;
+    __syncthreads();
+    if (threadIdx.x == 0) sm.w_valid = 0;  // AUG is this step's from here on
     if (threadIdx.x == 0) sm.entries_read += M * k;
     if (isinf(cmax)) {
         if (threadIdx.x == 0) { sm.status = -6; sm.phase = PH_DONE; }
@@ -1644,19 +1739,31 @@ DI void maxvol_step(const TaskDesc& td, Team& tm, int transpose, int lds_b_bytes
         }
         bsel = bsel && started;
     }
+    // binary64 warm steps keep C[X,:]^{-1} current through the swaps for the
+    // next step (the binary32 path solves every step)
+    const int wmaint = (sizeof(T) == 8 && started) ? 1 : 0;
     int swaps;
     if constexpr (std::is_same<T, float>::value && KMAX <= 32 && LDSB) {
         if (bsel) {
             swaps = swap_phase_bsel<T, KMAX>(td, tm, transpose, keff);
         } else {
             basis_phase<T, KMAX, LDSB>(td, tm, transpose, started, keff);
-            swaps = swap_phase<T, KMAX, LDSB>(td, tm, transpose, keff);
+            swaps = swap_phase<T, KMAX, LDSB>(td, tm, transpose, keff, wmaint);
         }
     } else {
         basis_phase<T, KMAX, LDSB>(td, tm, transpose, started, keff);
-        swaps = swap_phase<T, KMAX, LDSB>(td, tm, transpose, keff);
+        swaps = swap_phase<T, KMAX, LDSB>(td, tm, transpose, keff, wmaint);
     }
     if (swaps < 0) return;
+    if (wmaint) {
+        if (threadIdx.x == 0) sm.w_valid = 1;
+        // a copy in the problem's work buffer for a later launch (serving)
+        if (tm.rank == 0 && td.work) {
+            GL T* wg = gl((T*)td.work);
+            const T* Wr = (const T*)sm.AUG + KMAX;
+            for (int e = threadIdx.x; e < keff * keff; e += NT) wg[e] = Wr[(e / keff) * 2 * KMAX + e % keff];
+        }
+    }
     if (threadIdx.x == 0) {
         sm.swaps_total += swaps;
         if (keff < k) {
@@ -2109,6 +2216,7 @@ DI void final_core(const TaskDesc& td, Team& tio)
             } else {
                 sm.k = k + added;
                 sm.have_I = 0;
+                sm.w_valid = 0;
                 sm.sweep_in_level = 0;
                 sm.phase = PH_COL;
             }
@@ -2179,9 +2287,11 @@ NOINL void reduce_leader(const TaskDesc& td, Team& tio, int lds_b_bytes)
     sub.m = p;
     sub.n = p;
     sub.strip = sstrip;
+    sub.work = nullptr;  // the block lives there: no inverse is saved for a later launch
     if (threadIdx.x == 0) {
         sm.k = r;
         sm.have_I = 0;
+        sm.w_valid = 0;
     }
     if (threadIdx.x < r) sm.J[threadIdx.x] = threadIdx.x;
     __syncthreads();
@@ -2225,6 +2335,7 @@ NOINL void reduce_leader(const TaskDesc& td, Team& tio, int lds_b_bytes)
         if (threadIdx.x == 0) {
             sm.entries_read = er0 + (int64_t)p * p;
             sm.have_I = 1;
+            sm.w_valid = 0;
             sm.phase = PH_FINAL;
         }
     }
@@ -2254,6 +2365,7 @@ DI void load_state(const TaskDesc& td, Smem<T, KMAX>& sm)
         const int32_t swaps_total = __hip_atomic_load(&st->swaps_total, __ATOMIC_RELAXED, AGENT);
         const int32_t sweeps_done = __hip_atomic_load(&st->sweeps_done, __ATOMIC_RELAXED, AGENT);
         const int32_t phases_run = __hip_atomic_load(&st->phases_run, __ATOMIC_RELAXED, AGENT);
+        const int32_t w_valid = __hip_atomic_load(&st->w_valid, __ATOMIC_RELAXED, AGENT);
         const int64_t cand_next = __hip_atomic_load(&st->cand_next, __ATOMIC_RELAXED, AGENT);
         const int64_t entries_read = __hip_atomic_load(&st->entries_read, __ATOMIC_RELAXED, AGENT);
         const double est_rel = __hip_atomic_load(&st->est_rel, __ATOMIC_RELAXED, AGENT);
@@ -2272,6 +2384,7 @@ DI void load_state(const TaskDesc& td, Smem<T, KMAX>& sm)
         sm.swaps_total = swaps_total;
         sm.sweeps_done = sweeps_done;
         sm.phases_run = phases_run;
+        sm.w_valid = w_valid;
         sm.cand_next = cand_next;
         sm.entries_read = entries_read;
         sm.est_rel = est_rel;
@@ -2334,6 +2447,7 @@ DI void store_state(const TaskDesc& td, Smem<T, KMAX>& sm)
         v.var = sm.var;
         v.cond1 = sm.cond1;
         v.phases_run = sm.phases_run;
+        v.w_valid = sm.w_valid;
         __hip_atomic_store(&st->phase, v.phase, __ATOMIC_RELAXED, AGENT);
         __hip_atomic_store(&st->k, v.k, __ATOMIC_RELAXED, AGENT);
         __hip_atomic_store(&st->sweep_in_level, v.sweep_in_level, __ATOMIC_RELAXED, AGENT);
@@ -2345,6 +2459,7 @@ DI void store_state(const TaskDesc& td, Smem<T, KMAX>& sm)
         __hip_atomic_store(&st->swaps_total, v.swaps_total, __ATOMIC_RELAXED, AGENT);
         __hip_atomic_store(&st->sweeps_done, v.sweeps_done, __ATOMIC_RELAXED, AGENT);
         __hip_atomic_store(&st->phases_run, v.phases_run, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(&st->w_valid, v.w_valid, __ATOMIC_RELAXED, AGENT);
         __hip_atomic_store(&st->cand_next, v.cand_next, __ATOMIC_RELAXED, AGENT);
         __hip_atomic_store(&st->entries_read, v.entries_read, __ATOMIC_RELAXED, AGENT);
         __hip_atomic_store(&st->est_rel, v.est_rel, __ATOMIC_RELAXED, AGENT);
@@ -2362,6 +2477,14 @@ DI void run_task(const TaskDesc& td, Team& tm, const EngineArgs& ea)
     Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
     const int lds_b = ea.lds_b[variant_of<T, KMAX>()];
     load_state(td, sm);
+    if (sm.w_valid) {
+        // resumed between steps: the last step's inverse from the work buffer
+        const GL T* wg = gl((const T*)td.work);
+        T* Wr = (T*)sm.AUG + KMAX;
+        const int k = sm.k;
+        for (int e = threadIdx.x; e < k * k; e += NT) Wr[(e / k) * 2 * KMAX + e % k] = wg[e];
+        __syncthreads();
+    }
     int budget = ea.phase_budget;
     while (sm.phase != PH_DONE && budget > 0) {
         --budget;

@@ -39,7 +39,7 @@ struct TaskState {
     int64_t entries_read;
     double est_rel, est_abs, mean, var, cond1;
     int32_t phases_run;
-    int32_t pad;
+    int32_t w_valid;         // the work buffer holds C[X,:]^{-1} of the last step (binary64)
 };
 
 // One C-A / CUR problem.

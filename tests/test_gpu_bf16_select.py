@@ -99,6 +99,11 @@ def test_bf16_select_dense_16384(ctx, team):
     ref64 = oracle.ca_cur(oracle.dense(A), 32, 4, 0.0, d.cand_cols, d.sample_rows, d.sample_cols)
     assert res.status == 0 and res.k == 32
     assert res.err_est_rel <= 1.5 * ref64.err_est_rel, (res.err_est_rel, ref64.err_est_rel)
+    # the shortlist path ran: after the LU start of the first column step it
+    # gathers that strip a second time, which the plain binary32 path does not
+    mixed = ctx.ca_cur(lra.dense(At), 32, 4, 0.0, init_cols=d.cand_cols, sample_rows=d.sample_rows,
+                       sample_cols=d.sample_cols, precision=lra.PREC_MIXED, team_wgs=team)
+    assert res.entries_read == mixed.entries_read + 16384 * 32, (res.entries_read, mixed.entries_read)
     # the estimate of the returned sets, recomputed by the oracle on the same sample
     chk = oracle.residual(oracle.dense(A), res.I, res.J, d.sample_rows, d.sample_cols)
     assert abs(chk["est_rel"] - res.err_est_rel) <= 1e-10
