@@ -61,7 +61,7 @@ typedef enum {
                                fixed per-device scratch (LRA_NOALLOC_SCRATCH_BYTES)   */
 } lra_status;
 
-typedef enum { LRA_SRC_DENSE = 0, LRA_SRC_CAUCHY = 1, LRA_SRC_INVDIST = 2 } lra_src_kind;
+typedef enum { LRA_SRC_DENSE = 0, LRA_SRC_CAUCHY = 1, LRA_SRC_INVDIST = 2, LRA_SRC_PREPROCESSED = 3 } lra_src_kind;
 typedef enum { LRA_F32 = 0, LRA_F64 = 1 } lra_dtype;
 /* Strip precision.  FP64: strips, basis and swaps in binary64.  MIXED:
  * strips, basis and swaps in binary32.  BF16SEL: binary32 strips; each
@@ -78,16 +78,29 @@ typedef enum { LRA_PREC_FP64 = 0, LRA_PREC_MIXED = 1, LRA_PREC_BF16SEL = 2 } lra
  *            (col_major = 0) or a[j*lda + i] (col_major = 1).
  *   CAUCHY : x (m) and y (n) device vectors of `dtype`; a(i,j) = 1/(x_i - y_j).
  *   INVDIST: x (m), y (n) points; a(i,j) = 1/|x_i - y_j|, 0 where they coincide.
+ *   PREPROCESSED: the dense m x n device matrix a (as DENSE) seen through
+ *            d-abridged Hadamard multipliers with random sign scaling on both
+ *            sides (Section 8.3, family (i); d = pre_depth, 1..8, 2^d must
+ *            divide m and n): the source is F A H with
+ *            F = D_F H_{m,d} / 2^{d/2}, H = H_{n,d} D_H / 2^{d/2},
+ *            H_{n,d} = H_{2^d} (Sylvester, entry (a,b) = (-1)^popcount(a & b))
+ *            Kronecker I_{n/2^d}, D_F = diag(+-1) from the top bits of
+ *            SplitMix64 stream pre_seed (value i), D_H from stream pre_seed + 1.
+ *            F and H are orthogonal, so a CUR C U R of F A H gives the LRA
+ *            F^T C U R H^T of A with the same error (Section 6.6), and the
+ *            sampled estimate of F A H estimates it.  Each entry sums 4^d
+ *            entries of A in binary64 (t outer, u inner).
  * Differences of point coordinates are always formed in binary64. */
 typedef struct lra_source {
     int32_t kind;        /* lra_src_kind */
     int32_t dtype;       /* lra_dtype    */
-    const void* a;       /* DENSE: device pointer */
+    const void* a;       /* DENSE / PREPROCESSED: device pointer */
     int64_t lda;
     int32_t col_major;
-    int32_t reserved;
+    int32_t pre_depth;   /* PREPROCESSED: recursion depth d */
     const void* x;       /* CAUCHY / INVDIST: device pointers */
     const void* y;
+    uint64_t pre_seed;   /* PREPROCESSED: sign streams pre_seed, pre_seed + 1 */
 } lra_source;
 
 /* Options; lra_default_options() fills the defaults shown. */

@@ -60,33 +60,6 @@ DI float kernel_entry<float>(int kind, double d)
     return kind == 1 ? r : (d == 0.0 ? 0.0f : fabsf(r));
 }
 
-template <typename T>
-DI T dense_entry(const DevSource& s, int64_t i, int64_t j);
-
-template <>
-DI double dense_entry<double>(const DevSource& s, int64_t i, int64_t j)
-{
-    int64_t off = s.col_major ? j * s.lda + i : i * s.lda + j;
-    return load_elem(s.a, s.dtype, off);
-}
-
-template <>
-DI float dense_entry<float>(const DevSource& s, int64_t i, int64_t j)
-{
-    int64_t off = s.col_major ? j * s.lda + i : i * s.lda + j;
-    return s.dtype == 0 ? ((const float*)s.a)[off] : (float)((const double*)s.a)[off];
-}
-
-template <typename T>
-DI T entry_t(const DevSource& s, int64_t i, int64_t j)
-{
-    if (s.kind == 0) return dense_entry<T>(s, i, j);
-    double d = load_elem(s.x, s.dtype, i) - load_elem(s.y, s.dtype, j);
-    return kernel_entry<T>(s.kind, d);
-}
-
-DI double entry64(const DevSource& s, int64_t i, int64_t j) { return entry_t<double>(s, i, j); }
-
 // Device allocations (sources, descriptors' arrays, control blocks, trace)
 // are accessed through global-address-space pointers: generic (flat)
 // accesses also count against the LDS wait counter, so that every wait for
@@ -103,6 +76,50 @@ DI const GL E* gptr(const void* p)
     return (const GL E*)p;
 }
 
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): value number ctr of stream
+// seed; the pre-processing signs are the top bits of its values.
+DI uint64_t splitmix64(uint64_t seed, uint64_t ctr)
+{
+    uint64_t z = seed + (ctr + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Entry (i, j) of F A H (kind 3): F = D_F H_{pm,d} / 2^{d/2} and
+// H = H_{pn,d} D_H / 2^{d/2} with the d-abridged Hadamard matrix
+// H_{n,d} = H_{2^d} (Sylvester, entry (a,b) = (-1)^popcount(a & b)) times
+// I_{n/2^d} in the Kronecker sense, and sign diagonals D_F, D_H from the
+// SplitMix64 streams seed and seed + 1.  The sum runs over the 2^d x 2^d
+// entries A[i mod s + t s, j mod s' + u s'] (s = pm / 2^d, s' = pn / 2^d),
+// t outer, u inner, in binary64; the signs and 2^-d are exact factors.
+// Out of line, with the source's fields by value: it is the slow path of the
+// batched gathers, whose other paths keep their operands in registers.
+template <typename E>
+__device__ __attribute__((noinline)) double preprocessed_entry(const void* ap, int64_t lda, int col_major, int d,
+                                                               uint64_t seed, int64_t pm, int64_t pn, int64_t i,
+                                                               int64_t j)
+{
+    const auto* a = gptr<E>(ap);
+    const int64_t bm = pm >> d, bn = pn >> d;
+    const int64_t ib = i / bm, ir = i - ib * bm, jb = j / bn, jr = j - jb * bn;
+    const int nb = 1 << d;
+    double acc = 0.0;
+    for (int t = 0; t < nb; ++t) {
+        const int64_t ii = ir + (int64_t)t * bm;
+        const int pt = __popcll((unsigned long long)(ib & t));
+        for (int u = 0; u < nb; ++u) {
+            const int64_t jj = jr + (int64_t)u * bn;
+            const double v = (double)a[col_major ? jj * lda + ii : ii * lda + jj];
+            const int neg = (pt + __popcll((unsigned long long)(u & jb))) & 1;
+            acc += neg ? -v : v;
+        }
+    }
+    const double sf = (splitmix64(seed, (uint64_t)i) >> 63) ? -1.0 : 1.0;
+    const double sh = (splitmix64(seed + 1, (uint64_t)j) >> 63) ? -1.0 : 1.0;
+    return acc * sf * sh * ldexp(1.0, -d);
+}
+
 // Entries (ri[n], cj[n]) of a batch, element type E of the source: every
 // load of the batch is unconditional, so all are in flight together.
 template <typename E, typename T, int N>
@@ -115,6 +132,10 @@ DI void entries_e(const DevSource& s, const int64_t* ri, const int64_t* cj, T* o
         for (int n = 0; n < N; ++n) v[n] = a[s.col_major ? cj[n] * s.lda + ri[n] : ri[n] * s.lda + cj[n]];
 #pragma unroll
         for (int n = 0; n < N; ++n) out[n] = (T)v[n];
+    } else if (s.kind == 3) {
+#pragma unroll
+        for (int n = 0; n < N; ++n)
+            out[n] = (T)preprocessed_entry<E>(s.a, s.lda, s.col_major, s.depth, s.seed, s.pm, s.pn, ri[n], cj[n]);
     } else {
         const auto* x = gptr<E>(s.x);
         const auto* y = gptr<E>(s.y);
@@ -440,7 +461,7 @@ DI double gather_rows(const DevSource& src, int transpose, const Smem<T, KMAX>& 
 {
     const DevSource s = src;  // read once: stores to a global strip could alias it
     double lmax = 0.0;
-    if (s.kind == 0) {
+    if (s.kind == 0 || s.kind == 3) {
         constexpr int CH = KMAX < 32 ? KMAX : 32;
         for (int r = tid; r < rw.nrows; r += nth) {
             const int64_t gi = rw.r0 + r;
@@ -1192,7 +1213,7 @@ NOINL double gather_phase(const TaskDesc& td, Team& tio, int transpose, int warm
     const int64_t* F = transpose ? sm.I : sm.J;
     int64_t R;
     const Rows<T> rw = slice_of<T, KMAX, LDSB>(td, tm, transpose, R);
-    if (td.src.kind != 0 && threadIdx.x < k)
+    if ((td.src.kind == 1 || td.src.kind == 2) && threadIdx.x < k)
         sm.pts[threadIdx.x] = transpose ? load_elem(td.src.x, td.src.dtype, F[threadIdx.x])
                                         : load_elem(td.src.y, td.src.dtype, F[threadIdx.x]);
     // the last step's inverse is carried on the binary64 path

@@ -7,14 +7,17 @@ namespace lra {
 
 // Entry source as the device sees it (device pointers).
 struct DevSource {
-    int32_t kind;       // 0 dense, 1 Cauchy 1/(x_i - y_j), 2 inverse distance 1/|x_i - y_j|
+    int32_t kind;       // 0 dense, 1 Cauchy 1/(x_i - y_j), 2 inverse distance 1/|x_i - y_j|,
+                        // 3 dense pre-processed by abridged Hadamard multipliers, F A H
     int32_t dtype;      // 0 float32, 1 float64
     const void* a;
     int64_t lda;
     int32_t col_major;
-    int32_t pad;
+    int32_t depth;      // kind 3: recursion depth d (2^d divides pm and pn)
     const void* x;
     const void* y;
+    uint64_t seed;      // kind 3: sign streams seed (rows) and seed + 1 (columns)
+    int64_t pm, pn;     // kind 3: dimensions of a
 };
 
 // PH_REDUCE: the Cynical step (an r x r generator inside the k x k one).

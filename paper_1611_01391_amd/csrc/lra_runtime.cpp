@@ -294,8 +294,37 @@ static bool src_ok(const lra_source* s)
     if (!s) return false;
     if (s->dtype != LRA_F32 && s->dtype != LRA_F64) return false;
     if (s->kind == LRA_SRC_DENSE) return s->a != nullptr && s->lda > 0;
+    if (s->kind == LRA_SRC_PREPROCESSED)
+        return s->a != nullptr && s->lda > 0 && s->pre_depth >= 1 && s->pre_depth <= 8;
     if (s->kind == LRA_SRC_CAUCHY || s->kind == LRA_SRC_INVDIST) return s->x && s->y;
     return false;
+}
+
+// The device view of a source of m x n entries.
+static DevSource dev_source(const lra_source* src, int64_t m, int64_t n)
+{
+    DevSource d;
+    std::memset(&d, 0, sizeof(d));
+    d.kind = src->kind;
+    d.dtype = src->dtype;
+    d.a = src->a;
+    d.lda = src->lda;
+    d.col_major = src->col_major ? 1 : 0;
+    d.depth = src->kind == LRA_SRC_PREPROCESSED ? src->pre_depth : 0;
+    d.x = src->x;
+    d.y = src->y;
+    d.seed = src->pre_seed;
+    d.pm = m;
+    d.pn = n;
+    return d;
+}
+
+// A pre-processed source needs 2^d to divide both dimensions.
+static bool shape_ok(const lra_source* src, int64_t m, int64_t n)
+{
+    if (src->kind != LRA_SRC_PREPROCESSED) return true;
+    const int64_t b = (int64_t)1 << src->pre_depth;
+    return m % b == 0 && n % b == 0;
 }
 
 // Host-side description of one problem before upload.
@@ -329,17 +358,12 @@ static lra_status make_prob(const lra_source* src, int64_t m, int64_t n, int k, 
     if (fixed_alg && tol > 0.0) return LRA_EINVAL;
     if (o->cur_rank > 0 && o->cur_rank < k && o->inner_sweeps < 1) return LRA_EINVAL;
     if (!(o->tau >= 0.0) || o->k_step < 1 || o->k_max > 64) return LRA_EINVAL;
-    if (src->kind == LRA_SRC_DENSE && src->lda < (src->col_major ? m : n)) return LRA_EINVAL;
+    if ((src->kind == LRA_SRC_DENSE || src->kind == LRA_SRC_PREPROCESSED) && src->lda < (src->col_major ? m : n))
+        return LRA_EINVAL;
+    if (!shape_ok(src, m, n)) return LRA_EINVAL;
     if (o->precision != LRA_PREC_FP64 && o->precision != LRA_PREC_MIXED && o->precision != LRA_PREC_BF16SEL)
         return LRA_EINVAL;
-    p.src.kind = src->kind;
-    p.src.dtype = src->dtype;
-    p.src.a = src->a;
-    p.src.lda = src->lda;
-    p.src.col_major = src->col_major ? 1 : 0;
-    p.src.pad = 0;
-    p.src.x = src->x;
-    p.src.y = src->y;
+    p.src = dev_source(src, m, n);
     p.m = m;
     p.n = n;
     p.k = k;
@@ -1063,7 +1087,9 @@ extern "C" lra_status lra_cur_factors(lra_ctx* ctx, const lra_source* src, int64
     if (!ctx || !src_ok(src) || m < 1 || n < 1 || k < 1 || !I || !J) return LRA_EINVAL;
     if (out_dtype != LRA_F32 && out_dtype != LRA_F64) return LRA_EINVAL;
     if (m * (int64_t)k >= ((int64_t)1 << 31) || n * (int64_t)k >= ((int64_t)1 << 31)) return LRA_EINVAL;
-    if (src->kind == LRA_SRC_DENSE && src->lda < (src->col_major ? m : n)) return LRA_EINVAL;
+    if ((src->kind == LRA_SRC_DENSE || src->kind == LRA_SRC_PREPROCESSED) && src->lda < (src->col_major ? m : n))
+        return LRA_EINVAL;
+    if (!shape_ok(src, m, n)) return LRA_EINVAL;
     for (int c = 0; c < k; ++c)
         if (I[c] < 0 || I[c] >= m || J[c] < 0 || J[c] >= n) return LRA_EINVAL;
     if (!C_out && !R_out) return LRA_OK;
@@ -1076,15 +1102,7 @@ extern "C" lra_status lra_cur_factors(lra_ctx* ctx, const lra_source* src, int64
     std::memcpy(h, I, 8 * (size_t)k);
     std::memcpy(h + k, J, 8 * (size_t)k);
     int64_t* d = (int64_t*)ctx->dev.p;
-    DevSource ds;
-    ds.kind = src->kind;
-    ds.dtype = src->dtype;
-    ds.a = src->a;
-    ds.lda = src->lda;
-    ds.col_major = src->col_major ? 1 : 0;
-    ds.pad = 0;
-    ds.x = src->x;
-    ds.y = src->y;
+    const DevSource ds = dev_source(src, m, n);
     HIP_TRY(hipMemcpyAsync(d, h, (size_t)bytes, hipMemcpyHostToDevice, ctx->stream));
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev0, ctx->stream));
     HIP_TRY(launch_factors(ds, m, n, k, d, d + k, out_dtype == LRA_F64, C_out, R_out, ctx->stream));

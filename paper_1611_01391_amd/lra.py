@@ -22,7 +22,7 @@ OK, TOL_NOT_MET, MAXVOL_CAP, NUMERICAL_RANK, PENDING = 0, 1, 2, 3, 4
 EINVAL, ERANK, ENOMEM, EBUDGET, EDEVICE, ENONFINITE, ESCRATCH = -1, -2, -3, -4, -5, -6, -7
 # fixed device workspace of lra_ca_cur_noalloc (LRA_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 64 << 20
-SRC_DENSE, SRC_CAUCHY, SRC_INVDIST = 0, 1, 2
+SRC_DENSE, SRC_CAUCHY, SRC_INVDIST, SRC_PREPROCESSED = 0, 1, 2, 3
 F32, F64 = 0, 1
 PREC_FP64, PREC_MIXED, PREC_BF16SEL = 0, 1, 2
 
@@ -41,8 +41,8 @@ class LraError(RuntimeError):
 
 class Source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("a", C.c_void_p), ("lda", C.c_int64),
-                ("col_major", C.c_int32), ("reserved", C.c_int32), ("x", C.c_void_p),
-                ("y", C.c_void_p)]
+                ("col_major", C.c_int32), ("pre_depth", C.c_int32), ("x", C.c_void_p),
+                ("y", C.c_void_p), ("pre_seed", C.c_uint64)]
 
 
 class Options(C.Structure):
@@ -198,6 +198,17 @@ def dense(A, col_major: bool = False) -> DeviceSource:
         lda = A.stride(0)
     s = Source(SRC_DENSE, _dtype_code(A), A.data_ptr(), lda, 1 if col_major else 0, 0, None, None)
     return DeviceSource(s, m, n, (A,))
+
+
+def preprocessed(A, depth: int, seed: int = 0, col_major: bool = False) -> DeviceSource:
+    """F A H: the dense device matrix A through d-abridged Hadamard
+    multipliers with random sign scaling on both sides (orthogonal F, H);
+    2^depth must divide both dimensions."""
+    src = dense(A, col_major)
+    src.struct.kind = SRC_PREPROCESSED
+    src.struct.pre_depth = int(depth)
+    src.struct.pre_seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    return src
 
 
 def cauchy(x, y) -> DeviceSource:

@@ -120,6 +120,23 @@ static void check_make_prob()
     CHECK(make_prob(&s, 100, 150, 8, 1, 0.0, &o, p, 0) == LRA_EINVAL);  // lda < n
     o.cur_rank = 9;
     CHECK(make_prob(&s, 100, 100, 8, 1, 0.0, &o, p, 0) == LRA_EINVAL);
+    // the pre-processed source: depth 1..8, 2^depth dividing both dimensions
+    lra_default_options(&o);
+    lra_source h = dense_src(128);
+    h.kind = LRA_SRC_PREPROCESSED;
+    h.pre_seed = 0x123456789abcdefull;
+    for (int d = 0; d <= 9; ++d) {
+        h.pre_depth = d;
+        const lra_status want = (d >= 1 && d <= 7) ? LRA_OK : LRA_EINVAL;  // 2^8 does not divide 128
+        CHECK(make_prob(&h, 256, 128, 8, 1, 0.0, &o, p, 0) == want);
+        if (want == LRA_OK) {
+            CHECK(p.src.kind == 3 && p.src.depth == d && p.src.seed == h.pre_seed);
+            CHECK(p.src.pm == 256 && p.src.pn == 128 && p.src.lda == 128);
+        }
+    }
+    h.pre_depth = 3;
+    CHECK(make_prob(&h, 100, 128, 8, 1, 0.0, &o, p, 0) == LRA_EINVAL);  // 8 does not divide 100
+    CHECK(make_prob(&h, 256, 129, 8, 1, 0.0, &o, p, 0) == LRA_EINVAL);  // lda < n
 }
 
 static void check_planning()
