@@ -269,6 +269,8 @@ def bench_dense(args, plain=False):
                      "est_rel": res.err_est_rel, "entries_read": int(res.entries_read)}
     if not plain:
         out["strip_gather"] = _strip_gather(ctx, torch, src, n, n, res, esz)
+        if args.precision == "fp64" or args.top_svd:
+            out["top_svd"] = _top_svd_leg(ctx, torch, src, n, n, res, esz, cpu=not args.no_cpu_baseline)
     ctx.close()
     del At
     return out
@@ -305,6 +307,55 @@ def _strip_gather(ctx, torch, src, m, n, res, esz, reps=50):
     log(f"# strip gather: {kms * 1e3:.1f} us, {g['achieved_GBps']:.0f} GB/s algorithmic"
         + (f", {g['dram_GBps']:.0f} GB/s DRAM" if dram else ""))
     return g
+
+
+def _top_svd_leg(ctx, torch, src, m, n, res, esz, reps=20, cpu=True):
+    """The LRA -> top SVD transition (Appendix D, Algorithm D.1) on the run's
+    own CUR: lra_cur_factors gives C and R in the source precision, then
+    lra_top_svd at r = k and r = k / 2, timed with HIP events around all of
+    its launches (TSQR levels, core, apply).  Parity: sigma and sampled
+    entries of S diag(sigma) T^T against the oracle on the same factors.
+    Algorithmic bytes: C and R read twice (QR and output), S and T^T written
+    in binary64."""
+    Cd, Rd = ctx.cur_factors(src, res.I, res.J)
+    k = res.k
+    out = {}
+    for r in (k, k // 2):
+        S = torch.empty(r * m, dtype=torch.float64, device="cuda")
+        T = torch.empty(r * n, dtype=torch.float64, device="cuda")
+        for _ in range(3):
+            ctx.top_svd(Cd, res.U, Rd, r, S_out=S, Tt_out=T)
+        torch.cuda.synchronize()
+        ctx.set_timing(True, reset=True)
+        for _ in range(reps):
+            Sv, sigma, Tv, pc, pr = ctx.top_svd(Cd, res.U, Rd, r, S_out=S, Tt_out=T)
+        st = ctx.stats()
+        ctx.set_timing(False, reset=False)
+        ms = st["engine_ms_total"] / reps
+        alg = 2 * (m * k + k * n) * esz + 8 * r * (m + n)
+        leg = {"r": r, "ms": ms, "launches_per_call": st["launches"] / reps, "algorithmic_bytes": alg,
+               "achieved_GBps": alg / (ms * 1e-3) / 1e9, "frac_hbm": alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "bound": "latency (k-step Householder and Jacobi chains on one workgroup)"}
+        if cpu:
+            from oracle.top_svd import top_svd as oracle_top_svd
+            Ch = Cd.cpu().numpy().astype(np.float64)
+            Rh = Rd.cpu().numpy().astype(np.float64)
+            t0 = time.perf_counter()
+            ref = oracle_top_svd(Ch, res.U, Rh, r)
+            leg["cpu_oracle_s"] = time.perf_counter() - t0
+            rng = np.random.default_rng(3)
+            ii, jj = rng.integers(0, m, 256), rng.integers(0, n, 256)
+            Sh, Th = Sv.cpu().numpy(), Tv.cpu().numpy()
+            got = np.einsum("ia,a,ai->i", Sh[ii], sigma, Th[:, jj])
+            want = np.einsum("ia,a,ai->i", ref.S[ii], ref.sigma, ref.Tt[:, jj])
+            leg["parity"] = {"pivots_equal": bool(np.array_equal(pc[:r], ref.piv_c[:r])
+                                                  and np.array_equal(pr[:r], ref.piv_r[:r])),
+                             "min_pivot_margin": ref.min_margin(r),
+                             "sigma_max_rel_diff": float(np.max(np.abs(sigma - ref.sigma)) / ref.sigma[0]),
+                             "lra_max_rel_diff_sampled": float(np.max(np.abs(got - want)) / ref.sigma[0])}
+        log(f"# top SVD r={r}: {ms * 1e3:.1f} us per call")
+        out[f"r{r}"] = leg
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -722,6 +773,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", choices=["fp64", "mixed", "bf16sel"], default="fp64")
+    ap.add_argument("--top-svd", action="store_true", help="dense: time lra_top_svd also without the CPU legs")
     ap.add_argument("--points", type=int, default=1 << 20, help="multipole: number of points")
     ap.add_argument("--mp-tol", type=float, default=1e-8, help="multipole: tolerance")
     ap.add_argument("--requests", type=int, default=1000, help="serve: number of requests")

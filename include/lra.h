@@ -250,6 +250,31 @@ lra_status lra_ca_cur_noalloc(lra_ctx* ctx, const lra_source* src, int64_t m, in
 lra_status lra_cur_factors(lra_ctx* ctx, const lra_source* src, int64_t m, int64_t n, int k,
                            const int64_t* I, const int64_t* J, int32_t out_dtype, void* C_out, void* R_out);
 
+/* The top SVD of an LRA (Appendix D, Algorithm D.1): given M ~ C W R with
+ * C (m x k, column-major, ldc >= m) and R (k x n, row-major, ldr >= n) in
+ * device memory (both of dtype LRA_F32 or LRA_F64, e.g. from
+ * lra_cur_factors) and W (k x k, row-major, binary64) in host memory (the
+ * nucleus of an lra_result), and a target rank 1 <= r <= k <= 64 with
+ * k <= m, n: the column-pivoted QR factors C P_C = Q_C R_C and
+ * R^T P_R = Q_R R_R are truncated to their first r columns and the r x r
+ * middle factor R_C[:r,:] P_C^T W P_R R_R[:r,:]^T is split by its SVD
+ * S_bar Sigma T_bar^T, so that S diag(sigma) T^T = Pi_C C W R Pi_R
+ * (Pi: the orthogonal projectors on the kept columns of Q_C and Q_R) with
+ * S = Q_C[:, :r] S_bar and T^T = T_bar^T Q_R[:, :r]^T.  Outputs, binary64:
+ * S (m x r, column-major, lds >= m, device), sigma (r, host, descending) and
+ * T^T (r x n, row-major, ldt >= n, device); piv_c and piv_r (host, k each,
+ * may be NULL) receive the column pivots of C and of R^T (rows of R).
+ * Every step runs on the device in binary64 (C and R are read once for the
+ * QR and once for the output); the call returns after the outputs are
+ * written.  Errors: LRA_EINVAL (bad sizes or pointers), LRA_ENONFINITE (W not
+ * finite), LRA_ERANK (a kept diagonal entry of R_C or R_R at most
+ * max(m, n) u |R[0,0]|, the rounding level of the QR: the factors have
+ * numerical rank below r; S, sigma and T^T untouched,
+ * the pivots still written), LRA_ENOMEM, LRA_EBUDGET, LRA_EDEVICE. */
+lra_status lra_top_svd(lra_ctx* ctx, int64_t m, int64_t n, int k, int r, int32_t dtype, const void* C,
+                       int64_t ldc, const double* W, const void* R, int64_t ldr, double* S, int64_t lds,
+                       double* sigma, double* Tt, int64_t ldt, int64_t* piv_c, int64_t* piv_r);
+
 /* The maxvol sub-algorithm alone on a tall device strip (m x k, column-major,
  * leading dimension ld >= m, element type `dtype`): locally maximal-volume
  * k x k row subset I (host, capacity k) such that every entry of

@@ -20,8 +20,9 @@ rows j.. is moved to position j (lowest index among equals), with the norms
 recomputed from the current matrix at every step; the recorded margin of a
 step is the relative gap between the largest and the second largest of those
 norms.  The SVD of the small factor is LAPACK's (numpy.linalg.svd).  A
-requested rank above that of C or R (|R_C[j,j]| or |R_R[j,j]| at most
-k u |R[0,0]| for some j < r) is reported as rank loss, status -2.
+requested rank above the numerical rank of C or R (|R_C[j,j]| or |R_R[j,j]|
+at most max(m, n) u |R[0,0]| for some j < r: the level of the rounding errors
+of a Householder QR of the tall factor) is reported as rank loss, status -2.
 """
 from __future__ import annotations
 
@@ -112,7 +113,8 @@ def top_svd(C: np.ndarray, W: np.ndarray, R: np.ndarray, r: int) -> TopSVD:
     Qc, Rc, pc, mc = householder_qrp(C)
     Qr, Rr, pr, mr = householder_qrp(R.T)
     dc, dr = np.abs(np.diag(Rc)), np.abs(np.diag(Rr))
-    bad = (dc[:r] <= k * U64 * dc[0]).any() or (dr[:r] <= k * U64 * dr[0]).any()
+    lim = max(m, n) * U64
+    bad = (dc[:r] <= lim * dc[0]).any() or (dr[:r] <= lim * dr[0]).any()
     if bad:
         z = np.zeros((0,))
         return TopSVD(-2, np.zeros((m, 0)), z, np.zeros((0, n)), pc, pr, mc, mr, dc, dr)

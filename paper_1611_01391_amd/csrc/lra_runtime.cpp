@@ -30,6 +30,18 @@ hipError_t launch_factors(const DevSource& src, int64_t m, int64_t n, int k, con
                           int out64, void* C, void* R, hipStream_t stream);
 hipError_t noalloc_scratch_init(int device);
 void* noalloc_scratch(int device);
+size_t core_out_bytes();
+hipError_t topsvd_set_attributes();
+hipError_t launch_tsqr(const void* xa, int64_t rows_a, int64_t lda, int dta, int nblk_a, double* out_a,
+                       const void* xb, int64_t rows_b, int64_t ldb, int dtb, int nblk_b, double* out_b, int k,
+                       hipStream_t stream);
+hipError_t launch_topsvd_core(const double* RC, const double* RR, const double* W, int k, int r, double rank_lim,
+                              void* out, hipStream_t stream);
+hipError_t launch_topsvd_apply(const void* C, int64_t ldc, const void* R, int64_t ldr, int dtype, int64_t m,
+                               int64_t n, int r, const void* core, double* S, int64_t lds, double* Tt, int64_t ldt,
+                               hipStream_t stream);
+void topsvd_core_fields(const void* host_copy, int32_t* status, int32_t* sweeps, const int32_t** pc,
+                        const int32_t** pr, const double** sigma);
 }  // namespace lra
 
 using namespace lra;
@@ -275,6 +287,12 @@ extern "C" lra_status lra_create(lra_ctx** out, void* stream, size_t budget)
                 return hip_fail(e, "hipFuncSetAttribute");
             }
         }
+    e = topsvd_set_attributes();
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return hip_fail(e, "hipFuncSetAttribute(top SVD)");
+    }
     // device address of this device's copy of the allocation-free entry
     // point's scratch array (once per device)
     e = noalloc_scratch_init(c->device);
@@ -1115,6 +1133,109 @@ extern "C" lra_status lra_cur_factors(lra_ctx* ctx, const lra_source* src, int64
         ctx->stats.last_engine_ms = ms;
         ctx->stats.engine_ms_total += ms;
     }
+    return LRA_OK;
+}
+
+// Rows of the next TSQR level: k rows per 256-row block of this one.
+static int64_t tsqr_blocks(int64_t rows) { return (rows + 255) / 256; }
+
+extern "C" lra_status lra_top_svd(lra_ctx* ctx, int64_t m, int64_t n, int k, int r, int32_t dtype, const void* C,
+                                  int64_t ldc, const double* W, const void* R, int64_t ldr, double* S, int64_t lds,
+                                  double* sigma, double* Tt, int64_t ldt, int64_t* piv_c, int64_t* piv_r)
+{
+    if (!ctx || !C || !W || !R || !S || !sigma || !Tt) return LRA_EINVAL;
+    if (k < 1 || k > 64 || r < 1 || r > k || m < k || n < k) return LRA_EINVAL;
+    if (dtype != LRA_F32 && dtype != LRA_F64) return LRA_EINVAL;
+    if (ldc < m || ldr < n || lds < m || ldt < n) return LRA_EINVAL;
+    if (m * (int64_t)k >= ((int64_t)1 << 40) || n * (int64_t)k >= ((int64_t)1 << 40)) return LRA_EINVAL;
+    for (int i = 0; i < k * k; ++i)
+        if (!std::isfinite(W[i])) return LRA_ENONFINITE;
+    // device workspace: two ping-pong level buffers per factor, W, the core block
+    const int64_t lvl_c = tsqr_blocks(m) * k * k, lvl_r = tsqr_blocks(n) * k * k;
+    const int64_t off_w = 2 * (lvl_c + lvl_r) * 8;
+    const int64_t off_core = align_up(off_w + 8 * (int64_t)k * k, 256);
+    const int64_t dev_bytes = off_core + (int64_t)core_out_bytes();
+    lra_status rs = ensure(ctx->dev, dev_bytes, false, ctx);
+    if (rs != LRA_OK) return rs;
+    const int64_t host_bytes = std::max<int64_t>(8 * (int64_t)k * k, (int64_t)core_out_bytes());
+    rs = ensure(ctx->host, host_bytes, true, ctx);
+    if (rs != LRA_OK) return rs;
+    double* d = (double*)ctx->dev.p;
+    double* bc[2] = {d, d + lvl_c};
+    double* br[2] = {d + 2 * lvl_c, d + 2 * lvl_c + lvl_r};
+    double* dw = (double*)((uint8_t*)ctx->dev.p + off_w);
+    void* dcore = (uint8_t*)ctx->dev.p + off_core;
+    std::memcpy(ctx->host.p, W, 8 * (size_t)k * k);
+    HIP_TRY(hipMemcpyAsync(dw, ctx->host.p, 8 * (size_t)k * k, hipMemcpyHostToDevice, ctx->stream));
+    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev0, ctx->stream));
+    // TSQR of C and of R^T (R row-major k x n is R^T column-major, ld ldr)
+    const void* xc = C;
+    const void* xr = R;
+    int64_t rc = m, rr = n, ldxc = ldc, ldxr = ldr;
+    int dtc = dtype, dtr = dtype;
+    int lc = 0, lr = 0;       // ping-pong index of the next output
+    bool done_c = false, done_r = false;
+    const double* RC = nullptr;
+    const double* RR = nullptr;
+    int launches = 0;
+    while (!done_c || !done_r) {
+        const int nbc = done_c ? 0 : (int)tsqr_blocks(rc);
+        const int nbr = done_r ? 0 : (int)tsqr_blocks(rr);
+        double* oc = bc[lc];
+        double* orr = br[lr];
+        HIP_TRY(launch_tsqr(xc, rc, ldxc, dtc, nbc, oc, xr, rr, ldxr, dtr, nbr, orr, k, ctx->stream));
+        ++launches;
+        if (!done_c) {
+            if (nbc == 1) {
+                done_c = true;
+                RC = oc;
+            } else {
+                xc = oc;
+                rc = (int64_t)nbc * k;
+                ldxc = rc;
+                dtc = LRA_F64;
+                lc ^= 1;
+            }
+        }
+        if (!done_r) {
+            if (nbr == 1) {
+                done_r = true;
+                RR = orr;
+            } else {
+                xr = orr;
+                rr = (int64_t)nbr * k;
+                ldxr = rr;
+                dtr = LRA_F64;
+                lr ^= 1;
+            }
+        }
+    }
+    HIP_TRY(launch_topsvd_core(RC, RR, dw, k, r, (double)std::max(m, n) * 0x1p-53, dcore, ctx->stream));
+    // the apply kernel leaves S and T^T alone when the core reports rank loss
+    HIP_TRY(launch_topsvd_apply(C, ldc, R, ldr, dtype, m, n, r, dcore, S, lds, Tt, ldt, ctx->stream));
+    if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev1, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ctx->host.p, dcore, core_out_bytes(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    int32_t st = 0, sweeps = 0;
+    const int32_t* pc = nullptr;
+    const int32_t* pr = nullptr;
+    const double* sg = nullptr;
+    topsvd_core_fields(ctx->host.p, &st, &sweeps, &pc, &pr, &sg);
+    if (piv_c)
+        for (int j = 0; j < k; ++j) piv_c[j] = pc[j];
+    if (piv_r)
+        for (int j = 0; j < k; ++j) piv_r[j] = pr[j];
+    ctx->stats.launches += launches + 2;
+    if (ctx->timing) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+        ctx->stats.last_engine_ms = ms;
+        ctx->stats.engine_ms_total += ms;
+    }
+    LRA_LOG(2, "top SVD: m %lld n %lld k %d r %d, %d TSQR launches, %d Jacobi sweeps, status %d", (long long)m,
+            (long long)n, k, r, launches, sweeps, st);
+    if (st != 0) return (lra_status)st;
+    for (int j = 0; j < r; ++j) sigma[j] = sg[j];
     return LRA_OK;
 }
 

@@ -30,7 +30,8 @@ PREC_FP64, PREC_MIXED, PREC_BF16SEL = 0, 1, 2
 EXPORTS = ["lra_default_options", "lra_create", "lra_destroy", "lra_ca_cur", "lra_maxvol",
            "lra_ca_cur_batched", "lra_submit", "lra_poll", "lra_wait", "lra_serve_config", "lra_set_timing",
            "lra_autotune_team", "lra_autotune_batched", "lra_tuning_save", "lra_tuning_load",
-           "lra_get_stats", "lra_status_str", "lra_version", "lra_ca_cur_noalloc", "lra_cur_factors"]
+           "lra_get_stats", "lra_status_str", "lra_version", "lra_ca_cur_noalloc", "lra_cur_factors",
+           "lra_top_svd"]
 
 
 class LraError(RuntimeError):
@@ -107,6 +108,9 @@ def lib():
         L.lra_ca_cur_noalloc.restype = C.c_int
         L.lra_cur_factors.argtypes = [P, C.POINTER(Source), C.c_int64, C.c_int64, C.c_int, P, P, C.c_int32, P, P]
         L.lra_cur_factors.restype = C.c_int
+        L.lra_top_svd.argtypes = [P, C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_int32, P, C.c_int64, P, P,
+                                  C.c_int64, P, C.c_int64, P, P, C.c_int64, P, P]
+        L.lra_top_svd.restype = C.c_int
         L.lra_maxvol.argtypes = [P, P, C.c_int32, C.c_int64, C.c_int64, C.c_int, C.c_double,
                                  C.c_int, P, P, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.lra_maxvol.restype = C.c_int
@@ -411,6 +415,44 @@ class Context:
         if st != OK:
             raise LraError(st, "lra_cur_factors")
         return C_out.view(k, src.m).t(), R_out.view(k, src.n)
+
+    # -- LRA -> top SVD ---------------------------------------------------
+    def top_svd(self, Cf, W, Rf, r: int, S_out=None, Tt_out=None):
+        """lra_top_svd: the rank-r top SVD S diag(sigma) T^T of the LRA
+        C W R.  Cf: m x k device tensor with stride(0) == 1 (a column-major
+        view, as cur_factors returns), Rf: k x n device tensor with
+        stride(1) == 1, both float32 or float64; W: k x k host array.
+        Returns (S: m x r column-major view, sigma: numpy array, Tt: r x n,
+        piv_c, piv_r)."""
+        import torch
+        _require_cuda(Cf)
+        _require_cuda(Rf)
+        m, k = Cf.shape
+        k2, n = Rf.shape
+        if k2 != k or Cf.dtype != Rf.dtype or Cf.dtype not in (torch.float32, torch.float64):
+            raise ValueError("C (m x k) and R (k x n) of one floating dtype")
+        if Cf.stride(0) != 1 and k > 1:
+            raise ValueError("C needs stride(0) == 1 (a column-major view)")
+        if Rf.stride(1) != 1 and n > 1:
+            raise ValueError("R needs stride(1) == 1 (row-major)")
+        ldc = Cf.stride(1) if k > 1 else m
+        ldr = Rf.stride(0) if k > 1 else n
+        Wh = np.ascontiguousarray(np.asarray(W, dtype=np.float64))
+        if Wh.shape != (k, k):
+            raise ValueError("W must be k x k")
+        if S_out is None:
+            S_out = torch.empty(r * m, dtype=torch.float64, device=Cf.device)
+        if Tt_out is None:
+            Tt_out = torch.empty(r * n, dtype=torch.float64, device=Cf.device)
+        sigma = np.zeros(r)
+        pc = np.zeros(k, dtype=np.int64)
+        pr = np.zeros(k, dtype=np.int64)
+        st = lib().lra_top_svd(self._h, m, n, k, int(r), F64 if Cf.dtype == torch.float64 else F32, Cf.data_ptr(),
+                               ldc, Wh.ctypes.data, Rf.data_ptr(), ldr, S_out.data_ptr(), m, sigma.ctypes.data,
+                               Tt_out.data_ptr(), n, pc.ctypes.data, pr.ctypes.data)
+        if st != OK:
+            raise LraError(st, "lra_top_svd")
+        return S_out.view(r, m).t(), sigma, Tt_out.view(r, n), pc, pr
 
     # -- maxvol alone -----------------------------------------------------
     def maxvol(self, strip, tau: float = 0.01, init=None, max_swaps: int = 0):

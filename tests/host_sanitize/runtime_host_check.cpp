@@ -30,6 +30,23 @@ hipError_t launch_factors(const DevSource&, int64_t, int64_t, int, const int64_t
 }
 hipError_t noalloc_scratch_init(int) { return hipErrorNoDevice; }
 void* noalloc_scratch(int) { return nullptr; }
+size_t core_out_bytes() { return 70000; }
+hipError_t topsvd_set_attributes() { return hipErrorNoDevice; }
+hipError_t launch_tsqr(const void*, int64_t, int64_t, int, int, double*, const void*, int64_t, int64_t, int, int,
+                       double*, int, hipStream_t)
+{
+    return hipErrorNoDevice;
+}
+hipError_t launch_topsvd_core(const double*, const double*, const double*, int, int, double, void*, hipStream_t)
+{
+    return hipErrorNoDevice;
+}
+hipError_t launch_topsvd_apply(const void*, int64_t, const void*, int64_t, int, int64_t, int64_t, int, const void*,
+                               double*, int64_t, double*, int64_t, hipStream_t)
+{
+    return hipErrorNoDevice;
+}
+void topsvd_core_fields(const void*, int32_t*, int32_t*, const int32_t**, const int32_t**, const double**) {}
 }  // namespace lra
 
 static int failures = 0;
