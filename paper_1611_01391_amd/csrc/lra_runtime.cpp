@@ -41,7 +41,7 @@ hipError_t launch_topsvd_apply(const void* C, int64_t ldc, const void* R, int64_
                                int64_t n, int r, const void* core, double* S, int64_t lds, double* Tt, int64_t ldt,
                                hipStream_t stream);
 void topsvd_core_fields(const void* host_copy, int32_t* status, int32_t* sweeps, const int32_t** pc,
-                        const int32_t** pr, const double** sigma);
+                        const int32_t** pr, const double** sigma, const int64_t** ticks);
 }  // namespace lra
 
 using namespace lra;
@@ -1220,7 +1220,8 @@ extern "C" lra_status lra_top_svd(lra_ctx* ctx, int64_t m, int64_t n, int k, int
     const int32_t* pc = nullptr;
     const int32_t* pr = nullptr;
     const double* sg = nullptr;
-    topsvd_core_fields(ctx->host.p, &st, &sweeps, &pc, &pr, &sg);
+    const int64_t* tk = nullptr;
+    topsvd_core_fields(ctx->host.p, &st, &sweeps, &pc, &pr, &sg, &tk);
     if (piv_c)
         for (int j = 0; j < k; ++j) piv_c[j] = pc[j];
     if (piv_r)
@@ -1234,6 +1235,12 @@ extern "C" lra_status lra_top_svd(lra_ctx* ctx, int64_t m, int64_t n, int k, int
     }
     LRA_LOG(2, "top SVD: m %lld n %lld k %d r %d, %d TSQR launches, %d Jacobi sweeps, status %d", (long long)m,
             (long long)n, k, r, launches, sweeps, st);
+    if (st == 0) {
+        const double us = 1e3 / (double)ctx->wall_rate_khz;
+        LRA_LOG(2, "top SVD core: QR %.1f us, middle %.1f us, Jacobi %.1f us, sort %.1f us, solves %.1f us",
+                (tk[1] - tk[0]) * us, (tk[2] - tk[1]) * us, (tk[3] - tk[2]) * us, (tk[4] - tk[3]) * us,
+                (tk[5] - tk[4]) * us);
+    }
     if (st != 0) return (lra_status)st;
     for (int j = 0; j < r; ++j) sigma[j] = sg[j];
     return LRA_OK;

@@ -46,7 +46,10 @@ hipError_t launch_topsvd_apply(const void*, int64_t, const void*, int64_t, int, 
 {
     return hipErrorNoDevice;
 }
-void topsvd_core_fields(const void*, int32_t*, int32_t*, const int32_t**, const int32_t**, const double**) {}
+void topsvd_core_fields(const void*, int32_t*, int32_t*, const int32_t**, const int32_t**, const double**,
+                        const int64_t**)
+{
+}
 }  // namespace lra
 
 static int failures = 0;
