@@ -13,6 +13,10 @@ legs ride along as objects of the same line:
                     binary32 oracle and error against the binary64 oracle
   bf16_select_path  the same with the BF16-shortlist selection (binary32
                     recheck), against the same two oracles
+  top_svd           the LRA -> top SVD transition on the headline CUR
+  ca_test_algorithms_and_preprocessing
+                    Tests 1, 3, 4, the truncated-nucleus Primitive CUR and
+                    C-A on F A H (abridged Hadamard, depth 3) at 16384^2
   plain_512         dense binary64 512 x 512, W = G1 G2 + 1e-8 E, k = 8,
                     3 sweeps
   cauchy_2p20       implicit a_ij = 1/(s_i - t_j), m = n = 2^20, adaptive k
@@ -356,6 +360,80 @@ def _top_svd_leg(ctx, torch, src, m, n, res, esz, reps=20, cpu=True):
         log(f"# top SVD r={r}: {ms * 1e3:.1f} us per call")
         out[f"r{r}"] = leg
     return out
+
+
+# ---------------------------------------------------------------------------
+# the fixed-rank algorithms of the C-A tests and pre-processed C-A, at the
+# dense 16384^2 float32 shape
+# ---------------------------------------------------------------------------
+
+def bench_variants(args, reps=10):
+    """On the headline matrix: Tests 1 (random I, J, U = A[I,J]^-1; Section
+    12.2), Tests 3 (random 64 x 64 generator -> Cynical 16 x 16) and Tests 4
+    (one C-A loop at width 64, then Cynical 16 x 16; Section 6.5), the
+    Primitive CUR with the nucleus truncated to rank 32 of a 64 x 64
+    generator (Section 6.5), and 4 C-A sweeps at k = 32 on F A H with depth-3
+    abridged scaled Hadamard multipliers (Section 8.3).  Each is timed with HIP
+    events (kernel time per call) and, in the CPU leg, run once by the oracle
+    (single thread) for the parity figures and the baseline."""
+    import torch
+
+    from paper_1611_01391_amd import lra
+
+    A, d = _dense_input(args)
+    n = A.shape[0]
+    At = torch.from_numpy(A).cuda()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(args.seed + 11)
+    cols64 = rng.choice(n, 64, replace=False).astype(np.int64)
+    rows64 = rng.choice(n, 64, replace=False).astype(np.int64)
+    base = dict(sample_rows=d.sample_rows, sample_cols=d.sample_cols)
+    dense_src = lra.dense(At)
+    pre_src = lra.preprocessed(At, 3, args.seed + 5)
+    cases = [
+        ("tests1_random_k32", dense_src, 32, 0, dict(init_cols=cols64[:32], init_rows=rows64[:32])),
+        ("tests3_cynical_64_to_16", dense_src, 64, 0, dict(init_cols=cols64, init_rows=rows64, cur_rank=16)),
+        ("tests4_loop_then_cynical_64_to_16", dense_src, 64, 1, dict(init_cols=cols64, cur_rank=16)),
+        ("primitive_64_nucleus_rank_32", dense_src, 64, 0, dict(init_cols=cols64, init_rows=rows64, nucleus_rank=32)),
+        ("preprocessed_depth3_k32", pre_src, 32, 4, dict(init_cols=d.cand_cols)),
+    ]
+    ctx = lra.Context()
+    out = {}
+    for name, src, k, sw, extra in cases:
+        kw = dict(base, **extra)
+        el, st, res = _timed_steps(ctx, torch, lambda: ctx.ca_cur(src, k, sw, 0.0, **kw), reps, 2)
+        kms = st["engine_ms_total"] / max(1, st["launches"])
+        leg = {"k": k, "sweeps": sw, "options": {a: b for a, b in extra.items() if a in ("cur_rank", "nucleus_rank")},
+               "kernel_ms": kms, "calls_per_s": reps / el, "status": int(res.status), "k_out": int(res.k),
+               "est_rel": res.err_est_rel, "entries_read": int(res.entries_read)}
+        # bytes of A read: 4 per entry, 4^3 entries of A per entry of F A H
+        per_entry = 4 * (64 if src is pre_src else 1)
+        leg["bytes_read_of_A"] = int(res.entries_read) * per_entry
+        leg["achieved_GBps"] = leg["bytes_read_of_A"] / (kms * 1e-3) / 1e9
+        leg["frac_hbm"] = leg["achieved_GBps"] / HBM_PEAK_GBS
+        log(f"# {name}: kernel {kms:.3f} ms, status {res.status}, k {res.k}, est_rel {res.err_est_rel:.3e}")
+        if not args.no_cpu_baseline:
+            import oracle
+            hs = oracle.abridged(A, 3, args.seed + 5) if src is pre_src else oracle.dense(A)
+            t0 = time.perf_counter()
+            if src is pre_src:
+                ref = oracle.ca_cur(hs, k, sw, 0.0, d.cand_cols, d.sample_rows, d.sample_cols)
+            else:
+                ref = oracle.cur_variant(hs, k, sw, kw["init_cols"], d.sample_rows, d.sample_cols,
+                                         init_rows=kw.get("init_rows"), cur_rank=kw.get("cur_rank", 0),
+                                         nucleus_rank=kw.get("nucleus_rank", 0))
+            t_cpu = time.perf_counter() - t0
+            leg["cpu_baseline"] = {"value": 1.0 / t_cpu, "unit": "calls/s", "cores": 1, "kind": "oracle",
+                                   "sample": "one call of the same algorithm on the same matrix"}
+            leg["parity"] = {"same_status_k": (int(ref.status), int(ref.k)) == (int(res.status), int(res.k)),
+                             "same_I": bool(np.array_equal(np.sort(ref.I), np.sort(res.I))),
+                             "same_J": bool(np.array_equal(np.sort(ref.J), np.sort(res.J))),
+                             "est_rel_oracle": ref.err_est_rel,
+                             "est_rel_abs_diff": abs(ref.err_est_rel - res.err_est_rel)}
+        out[name] = leg
+    ctx.close()
+    del At
+    return {"workload": f"dense float32 {n}x{n} (the headline matrix)", "cases": out}
 
 
 # ---------------------------------------------------------------------------
@@ -755,6 +833,8 @@ def bench_all(args):
     out["batched_vs_plain"] = dict(mp["batched_vs_plain"], config=mp["config"], roofline=mp["roofline"],
                                    cpu_baseline=mp["cpu_baseline"], result=mp["result"], wall_s=mp["wall_s"],
                                    kernel_ms=mp["roofline"]["kernel_ms"])
+    var = _leg("variants", bench_variants, args)
+    out["ca_test_algorithms_and_preprocessing"] = var
     sv = _leg("serve", bench_serve, args)
     out["served_vs_plain"] = dict(sv["served_vs_plain"], config=sv["config"], roofline=sv["roofline"],
                                   cpu_baseline=sv["cpu_baseline"], result=sv["result"], wall_s=sv["wall_s"])
@@ -767,7 +847,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["all", "dense", "plain", "cauchy", "multipole", "serve"], default="all")
+    ap.add_argument("--workload", choices=["all", "dense", "plain", "cauchy", "multipole", "serve", "variants"],
+                    default="all")
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--sweeps", type=int, default=4)
@@ -805,6 +886,8 @@ def main():
         out = bench_cauchy(args)
     elif args.workload == "multipole":
         out = bench_multipole(args)
+    elif args.workload == "variants":
+        out = bench_variants(args)
     else:
         out = bench_serve(args)
     print(json.dumps(out), flush=True)
