@@ -267,6 +267,7 @@ struct Smem {
     double est_rel, est_abs, mean, var, cond1;
     int32_t flag, fetch, ok, pivp;
     int32_t w_valid;          // AUG's right half holds C[X,:]^{-1} of the last step
+    int32_t jsweeps;          // Jacobi sweeps of the last truncated nucleus (trace)
     double minpiv;
 };
 
@@ -1882,6 +1883,27 @@ DI void block_sums(double (&v)[NV], Smem<T, KMAX>& sm)
 // nucleus U = A[I,J]^{-1} and the sampled residual (leader workgroup only)
 // ----------------------------------------------------------------------------
 
+template <int CTRL>
+DI double dpp_d(double v)
+{
+    const int64_t b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((int64_t)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over each aligned group of 8 lanes, the same bits in all 8: lane i
+// first adds lane 7 - i (row_half_mirror), then the partner in its quad at
+// distance 2 and 1; every lane ends with the same two partial sums, added in
+// either order.
+DI double sum8(double v)
+{
+    v += dpp_d<0x141>(v);
+    v += dpp_d<0x4E>(v);
+    v += dpp_d<0xB1>(v);
+    return v;
+}
+
 // The Primitive algorithm's nucleus (Section 6.5): U = (G)_r^+, the
 // pseudo-inverse of the rank-r truncation of the generator, by the one-sided
 // Jacobi method (Hestenes): W = G V with V = I at the start, rotating column
@@ -1893,13 +1915,29 @@ DI void block_sums(double (&v)[NV], Smem<T, KMAX>& sm)
 // r largest (ties: smaller j) U[a][b] = sum_t V[a][j_t] W[b][j_t] / sigma^2.
 // F = [G | I | A[I,S]] (row stride LDF) on entry; on exit the middle block
 // holds U and the right block U A[I,S]; sm.ok = (sigma_{j_r} > 0).
+// jb: when F lives in global memory, LDS room for W and V (2 KMAX (KMAX + 1)
+// doubles): the sweeps run there (odd row stride: the 8 rows a lane group
+// reads fall in different banks), and the result is copied back; nullptr:
+// the sweeps run on F in place.
 template <typename T, int KMAX, int LDF>
-DI void jacobi_pinv(double* F, int k, int r, int s, Smem<T, KMAX>& sm)
+DI void jacobi_pinv(double* F, int k, int r, int s, Smem<T, KMAX>& sm, double* jb)
 {
     const int kk = k + (k & 1);
     const int npair = kk / 2;
     const int grp = threadIdx.x >> 3, g8 = threadIdx.x & 7;
     const double eps = (double)k * 0x1p-53;
+    constexpr int JLD = KMAX + 1;
+    double* Wb = jb ? jb : F;
+    double* Vb = jb ? jb + KMAX * JLD : F + KMAX;
+    const int ld = jb ? JLD : LDF;
+    if (jb) {
+        for (int e = threadIdx.x; e < k * k; e += NT) {
+            const int i = e / k, c = e - i * k;
+            Wb[i * JLD + c] = F[i * LDF + c];
+            Vb[i * JLD + c] = F[i * LDF + KMAX + c];
+        }
+        __syncthreads();
+    }
     for (int sweep = 0; sweep < 100; ++sweep) {
         if (threadIdx.x == 0) sm.flag = 0;
         __syncthreads();
@@ -1909,32 +1947,44 @@ DI void jacobi_pinv(double* F, int k, int r, int s, Smem<T, KMAX>& sm)
                 const int pa = a == 0 ? 0 : (a - 1 + round) % (kk - 1) + 1;
                 const int pb = (b - 1 + round) % (kk - 1) + 1;
                 const int P = pa < pb ? pa : pb, Qc = pa < pb ? pb : pa;
+                // whole 8-lane groups take this branch together (DPP sums)
                 if (Qc < k) {
-                    double al = 0.0, be = 0.0, ga = 0.0;
-                    for (int i = g8; i < k; i += 8) {
-                        const double wp = F[i * LDF + P], wq = F[i * LDF + Qc];
-                        al += wp * wp;
-                        be += wq * wq;
-                        ga += wp * wq;
-                    }
+                    // rows g8, g8 + 8, ...: every load before any store
+                    constexpr int RPT = (KMAX + 7) / 8;
+                    double wp[RPT], wq[RPT], vp[RPT], vq[RPT];
 #pragma unroll
-                    for (int o = 4; o >= 1; o >>= 1) {
-                        al += __shfl_xor(al, o, 64);
-                        be += __shfl_xor(be, o, 64);
-                        ga += __shfl_xor(ga, o, 64);
+                    for (int e = 0; e < RPT; ++e) {
+                        const int i = g8 + 8 * e < k ? g8 + 8 * e : g8;
+                        wp[e] = Wb[i * ld + P];
+                        wq[e] = Wb[i * ld + Qc];
+                        vp[e] = Vb[i * ld + P];
+                        vq[e] = Vb[i * ld + Qc];
                     }
+                    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                    for (int e = 0; e < RPT; ++e)
+                        if (g8 + 8 * e < k) {
+                            al += wp[e] * wp[e];
+                            be += wq[e] * wq[e];
+                            ga += wp[e] * wq[e];
+                        }
+                    al = sum8(al);
+                    be = sum8(be);
+                    ga = sum8(ga);
                     if (fabs(ga) > eps * sqrt(al * be)) {
                         const double zeta = (be - al) / (2.0 * ga);
                         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                         const double c = 1.0 / sqrt(1.0 + t * t);
                         const double sn = c * t;
-                        for (int i = g8; i < k; i += 8) {
-                            const double wp = F[i * LDF + P], wq = F[i * LDF + Qc];
-                            F[i * LDF + P] = c * wp - sn * wq;
-                            F[i * LDF + Qc] = sn * wp + c * wq;
-                            const double vp = F[i * LDF + KMAX + P], vq = F[i * LDF + KMAX + Qc];
-                            F[i * LDF + KMAX + P] = c * vp - sn * vq;
-                            F[i * LDF + KMAX + Qc] = sn * vp + c * vq;
+#pragma unroll
+                        for (int e = 0; e < RPT; ++e) {
+                            const int i = g8 + 8 * e;
+                            if (i < k) {
+                                Wb[i * ld + P] = c * wp[e] - sn * wq[e];
+                                Wb[i * ld + Qc] = sn * wp[e] + c * wq[e];
+                                Vb[i * ld + P] = c * vp[e] - sn * vq[e];
+                                Vb[i * ld + Qc] = sn * vp[e] + c * vq[e];
+                            }
                         }
                         if (g8 == 0) sm.flag = 1;
                     }
@@ -1945,7 +1995,17 @@ DI void jacobi_pinv(double* F, int k, int r, int s, Smem<T, KMAX>& sm)
         }
         const int rotated = sm.flag;
         __syncthreads();
+        if (threadIdx.x == 0) sm.jsweeps = sweep + 1;
         if (!rotated) break;
+    }
+    if (jb) {
+        for (int e = threadIdx.x; e < k * k; e += NT) {
+            const int i = e / k, c = e - i * k;
+            F[i * LDF + c] = Wb[i * JLD + c];
+            F[i * LDF + KMAX + c] = Vb[i * JLD + c];
+        }
+        __threadfence_block();
+        __syncthreads();
     }
     // singular values and their order (decreasing; ties by index)
     double* sv = sm.pts;
@@ -2014,7 +2074,7 @@ DI void jacobi_pinv(double* F, int k, int r, int s, Smem<T, KMAX>& sm)
 // problem's global work buffer); a compile-time choice keeps LDS accesses
 // ds_* instructions.
 template <typename T, int KMAX, bool FLDS>
-DI void final_core(const TaskDesc& td, Team& tio)
+DI void final_core(const TaskDesc& td, Team& tio, int lds_b_bytes)
 {
     Team tm = tio;
     Smem<T, KMAX>& sm = smem_ref<T, KMAX>();
@@ -2082,7 +2142,10 @@ DI void final_core(const TaskDesc& td, Team& tio)
                 j = Si[e % s];
             },
             [&](int e, double v) { E[e] = v; });
-        jacobi_pinv<T, KMAX, LDF>(Fm, k, ntr, s, sm);
+        // work matrices in global memory: the sweeps run in the (now unused)
+        // strip LDS when W and V fit there
+        const bool stage = !FLDS && (int64_t)2 * KMAX * (KMAX + 1) * 8 <= lds_b_bytes;
+        jacobi_pinv<T, KMAX, LDF>(Fm, k, ntr, s, sm, stage ? (double*)blds_ptr<T, KMAX>() : nullptr);
     } else if (k <= K32 && s <= 64) {
         const int wv = threadIdx.x >> 6;
         if (wv == 0) {
@@ -2252,8 +2315,8 @@ NOINL void final_leader(const TaskDesc& td, Team& tio, int lds_b_bytes)
 {
     constexpr int LDF = 2 * KMAX + 64;
     const int64_t need = (int64_t)KMAX * LDF + (int64_t)td.q * smem_ref<T, KMAX>().k + (int64_t)td.q * td.s;
-    if (need * 8 <= lds_b_bytes) final_core<T, KMAX, true>(td, tio);
-    else final_core<T, KMAX, false>(td, tio);
+    if (need * 8 <= lds_b_bytes) final_core<T, KMAX, true>(td, tio, lds_b_bytes);
+    else final_core<T, KMAX, false>(td, tio, lds_b_bytes);
 }
 
 // ----------------------------------------------------------------------------
@@ -2555,9 +2618,10 @@ DI void run_task(const TaskDesc& td, Team& tm, const EngineArgs& ea)
             }
         } else {  // PH_FINAL
             trace_ev(tm, EV_FINAL_BEGIN, 0);
+            if (threadIdx.x == 0) sm.jsweeps = 0;
             write_factors<T, KMAX>(td, sm, tm);
             if (tm.rank == 0) final_leader<T, KMAX>(td, tm, lds_b);
-            trace_ev(tm, EV_FINAL_END, 0);
+            trace_ev(tm, EV_FINAL_END, sm.jsweeps);
             if (tm.size > 1) {
                 // the leader's decision reaches the team through global memory
                 if (tm.rank == 0) store_state(td, sm);
