@@ -94,30 +94,61 @@ DI uint64_t splitmix64(uint64_t seed, uint64_t ctr)
 // entries A[i mod s + t s, j mod s' + u s'] (s = pm / 2^d, s' = pn / 2^d),
 // t outer, u inner, in binary64; the signs and 2^-d are exact factors.
 // Out of line, with the source's fields by value: it is the slow path of the
-// batched gathers, whose other paths keep their operands in registers.
+// batched gathers, whose other paths keep their operands in registers.  Two
+// entries per call, so that their loads are in flight together.
+struct Pair {
+    double a, b;
+};
+
 template <typename E>
-__device__ __attribute__((noinline)) double preprocessed_entry(const void* ap, int64_t lda, int col_major, int d,
-                                                               uint64_t seed, int64_t pm, int64_t pn, int64_t i,
-                                                               int64_t j)
+__device__ __attribute__((noinline)) Pair preprocessed_pair(const void* ap, int64_t lda, int col_major, int d,
+                                                            uint64_t seed, int64_t pm, int64_t pn, int64_t i0,
+                                                            int64_t j0, int64_t i1, int64_t j1)
 {
     const auto* a = gptr<E>(ap);
     const int64_t bm = pm >> d, bn = pn >> d;
-    const int64_t ib = i / bm, ir = i - ib * bm, jb = j / bn, jr = j - jb * bn;
-    const int nb = 1 << d;
-    double acc = 0.0;
-    for (int t = 0; t < nb; ++t) {
-        const int64_t ii = ir + (int64_t)t * bm;
-        const int pt = __popcll((unsigned long long)(ib & t));
-        for (int u = 0; u < nb; ++u) {
-            const int64_t jj = jr + (int64_t)u * bn;
-            const double v = (double)a[col_major ? jj * lda + ii : ii * lda + jj];
-            const int neg = (pt + __popcll((unsigned long long)(u & jb))) & 1;
-            acc += neg ? -v : v;
-        }
+    const int nb = 1 << d, nn = nb * nb;
+    int64_t ib[2], ir[2], jb[2], jr[2];
+    ib[0] = i0 / bm;
+    ir[0] = i0 - ib[0] * bm;
+    jb[0] = j0 / bn;
+    jr[0] = j0 - jb[0] * bn;
+    ib[1] = i1 / bm;
+    ir[1] = i1 - ib[1] * bm;
+    jb[1] = j1 / bn;
+    jr[1] = j1 - jb[1] * bn;
+    // the 4^d terms of each entry in the order e = t 2^d + u, loaded 16 at a
+    // time (indices past the end repeat the chunk's first) and added in that
+    // order
+    double acc[2] = {0.0, 0.0};
+    for (int e0 = 0; e0 < nn; e0 += 16) {
+        double v[2][16];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int e = e0 + q < nn ? e0 + q : e0;
+                const int64_t ii = ir[p] + (int64_t)(e >> d) * bm, jj = jr[p] + (int64_t)(e & (nb - 1)) * bn;
+                v[p][q] = (double)a[col_major ? jj * lda + ii : ii * lda + jj];
+            }
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int e = e0 + q;
+                if (e < nn) {
+                    const int neg = (__popcll((unsigned long long)(ib[p] & (e >> d))) +
+                                     __popcll((unsigned long long)((e & (nb - 1)) & jb[p]))) & 1;
+                    acc[p] += neg ? -v[p][q] : v[p][q];
+                }
+            }
     }
-    const double sf = (splitmix64(seed, (uint64_t)i) >> 63) ? -1.0 : 1.0;
-    const double sh = (splitmix64(seed + 1, (uint64_t)j) >> 63) ? -1.0 : 1.0;
-    return acc * sf * sh * ldexp(1.0, -d);
+    Pair out;
+    out.a = acc[0] * ((splitmix64(seed, (uint64_t)i0) >> 63) ? -1.0 : 1.0) *
+            ((splitmix64(seed + 1, (uint64_t)j0) >> 63) ? -1.0 : 1.0) * ldexp(1.0, -d);
+    out.b = acc[1] * ((splitmix64(seed, (uint64_t)i1) >> 63) ? -1.0 : 1.0) *
+            ((splitmix64(seed + 1, (uint64_t)j1) >> 63) ? -1.0 : 1.0) * ldexp(1.0, -d);
+    return out;
 }
 
 // Entries (ri[n], cj[n]) of a batch, element type E of the source: every
@@ -134,8 +165,13 @@ DI void entries_e(const DevSource& s, const int64_t* ri, const int64_t* cj, T* o
         for (int n = 0; n < N; ++n) out[n] = (T)v[n];
     } else if (s.kind == 3) {
 #pragma unroll
-        for (int n = 0; n < N; ++n)
-            out[n] = (T)preprocessed_entry<E>(s.a, s.lda, s.col_major, s.depth, s.seed, s.pm, s.pn, ri[n], cj[n]);
+        for (int n = 0; n < N; n += 2) {
+            const int n1 = n + 1 < N ? n + 1 : n;
+            const Pair pr = preprocessed_pair<E>(s.a, s.lda, s.col_major, s.depth, s.seed, s.pm, s.pn, ri[n], cj[n],
+                                                 ri[n1], cj[n1]);
+            out[n] = (T)pr.a;
+            if (n + 1 < N) out[n + 1] = (T)pr.b;
+        }
     } else {
         const auto* x = gptr<E>(s.x);
         const auto* y = gptr<E>(s.y);
