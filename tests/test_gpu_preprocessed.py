@@ -103,6 +103,19 @@ def test_preprocessed_binary32(ctx, seed):
         assert abs(res.err_est_rel - ref.err_est_rel) <= 1e-9 * ref.err_est_rel + 1e-15
 
 
+def test_preprocessed_dense_16384(ctx):
+    """The dense 16384 x 16384 float32 workload through depth-3 multipliers
+    (seed 5), k = 32, 4 sweeps, in the benchmark's configuration."""
+    from paper_1611_01391_amd import lra
+    _say("preprocessed dense 16384 depth 3")
+    A, d = synth.dense_scaled(0)
+    res = ctx.ca_cur(lra.preprocessed(torch.from_numpy(A).cuda(), 3, 5), 32, 4, 0.0, init_cols=d.cand_cols,
+                     sample_rows=d.sample_rows, sample_cols=d.sample_cols)
+    ref = oracle.ca_cur(oracle.abridged(A, 3, 5), 32, 4, 0.0, d.cand_cols, d.sample_rows, d.sample_cols)
+    assert _same_sets(res, ref, "dense 16384 depth 3")
+    assert res.entries_read == ref.entries_read
+
+
 def test_factors_bitwise_and_recovery(ctx):
     from paper_1611_01391_amd import lra
     _say("preprocessed factors and recovery")

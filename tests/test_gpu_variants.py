@@ -161,6 +161,36 @@ def test_primitive_large_rank(ctx):
     assert abs(res.err_est_rel - ref.err_est_rel) <= 1e-10 + 1e-6 * ref.err_est_rel
 
 
+@pytest.mark.parametrize("case", ["tests1", "tests3", "tests4", "primitive"])
+def test_variants_dense_16384(ctx, case):
+    """The dense 16384 x 16384 float32 workload in the benchmark's
+    configuration: random 64-column and 64-row draws of seed 11, Tests 1 at
+    k = 32, Tests 3 and 4 from 64 x 64 to 16 x 16, the Primitive CUR of a
+    64 x 64 generator at nucleus rank 32."""
+    from paper_1611_01391_amd import lra
+    _say(f"variants dense 16384 {case}")
+    A, d = synth.dense_scaled(0)
+    n = A.shape[0]
+    rng = np.random.default_rng(11)
+    cols64 = rng.choice(n, 64, replace=False).astype(np.int64)
+    rows64 = rng.choice(n, 64, replace=False).astype(np.int64)
+    spec = {"tests1": (32, 0, dict(init_cols=cols64[:32], init_rows=rows64[:32])),
+            "tests3": (64, 0, dict(init_cols=cols64, init_rows=rows64, cur_rank=16)),
+            "tests4": (64, 1, dict(init_cols=cols64, cur_rank=16)),
+            "primitive": (64, 0, dict(init_cols=cols64, init_rows=rows64, nucleus_rank=32))}[case]
+    k, sw, kw = spec
+    res = ctx.ca_cur(lra.dense(torch.from_numpy(A).cuda()), k, sw, 0.0, sample_rows=d.sample_rows,
+                     sample_cols=d.sample_cols, **kw)
+    ref = oracle.cur_variant(oracle.dense(A), k, sw, kw["init_cols"], d.sample_rows, d.sample_cols,
+                             init_rows=kw.get("init_rows"), cur_rank=kw.get("cur_rank", 0),
+                             nucleus_rank=kw.get("nucleus_rank", 0))
+    assert _compare(res, ref, GAMMA64, f"dense 16384 {case}", est_tol=1e-10 * max(1.0, ref.err_est_rel))
+    if case == "primitive":
+        s = np.linalg.svd(ref.G, compute_uv=False)
+        tol = 1e-9 * s[0] / s[31] * np.abs(ref.U).max()
+        np.testing.assert_allclose(res.U, ref.U, rtol=0, atol=tol)
+
+
 def test_variants_batched_equal_single(ctx):
     """Cynical and Primitive problems inside one batched launch return the
     same bits as alone (default draws: stream seed + block index, random
