@@ -266,8 +266,8 @@ lra_status lra_cur_factors(lra_ctx* ctx, const lra_source* src, int64_t m, int64
  * may be NULL) receive the column pivots of C and of R^T (rows of R).
  * Every step runs on the device in binary64 (C and R are read once for the
  * QR and once for the output); the call returns after the outputs are
- * written.  Errors: LRA_EINVAL (bad sizes or pointers), LRA_ENONFINITE (W not
- * finite), LRA_ERANK (a kept diagonal entry of R_C or R_R at most
+ * written.  Errors: LRA_EINVAL (bad sizes or pointers), LRA_ENONFINITE (W, C or
+ * R not finite; no output written), LRA_ERANK (a kept diagonal entry of R_C or R_R at most
  * max(m, n) u |R[0,0]|, the rounding level of the QR: the factors have
  * numerical rank below r; S, sigma and T^T untouched,
  * the pivots still written), LRA_ENOMEM, LRA_EBUDGET, LRA_EDEVICE. */

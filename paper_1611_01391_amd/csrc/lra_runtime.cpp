@@ -1222,9 +1222,9 @@ extern "C" lra_status lra_top_svd(lra_ctx* ctx, int64_t m, int64_t n, int k, int
     const double* sg = nullptr;
     const int64_t* tk = nullptr;
     topsvd_core_fields(ctx->host.p, &st, &sweeps, &pc, &pr, &sg, &tk);
-    if (piv_c)
+    if (piv_c && st != LRA_ENONFINITE)
         for (int j = 0; j < k; ++j) piv_c[j] = pc[j];
-    if (piv_r)
+    if (piv_r && st != LRA_ENONFINITE)
         for (int j = 0; j < k; ++j) piv_r[j] = pr[j];
     ctx->stats.launches += launches + 2;
     if (ctx->timing) {

@@ -44,7 +44,7 @@ struct TallLevel {
 
 // Outputs of the core kernel (device workspace).
 struct CoreOut {
-    int32_t status;       // 0, or -2 (a kept pivot of C or R^T is at rounding level)
+    int32_t status;       // 0, -2 (a kept pivot of C or R^T at rounding level) or -6 (NaN / Inf)
     int32_t sweeps;       // Jacobi sweeps
     int64_t tick[6];      // wall clock at the core's stage boundaries (diagnostics)
     int32_t pc[TS_KMAX];  // column pivots of C
@@ -395,12 +395,19 @@ __global__ __launch_bounds__(256) void topsvd_core_kernel(const double* RC, cons
     int32_t* flag = pr + 64;                 // 68: rotations in the sweep; sort ranks
     const int t = threadIdx.x;
     if (t == 0) out->tick[0] = wall_clock64();
+    // a NaN or Inf anywhere in C or R reaches the triangles
+    int nonfinite = 0;
     for (int e = t; e < k * k; e += 256) {
         const int c = e / k, i = e - c * k;
-        A1[c * CORE_LD + i] = RC[c * k + i];
-        A2[c * CORE_LD + i] = RR[c * k + i];
+        const double x1 = RC[c * k + i], x2 = RR[c * k + i];
+        nonfinite |= !(fabs(x1) <= 1.7976931348623157e308) || !(fabs(x2) <= 1.7976931348623157e308);
+        A1[c * CORE_LD + i] = x1;
+        A2[c * CORE_LD + i] = x2;
     }
-    __syncthreads();
+    if (__syncthreads_or(nonfinite)) {
+        if (t == 0) out->status = -6;
+        return;
+    }
     // the two pivoted QRs run side by side on wavefronts 0 and 1
     if (k <= 32) {
         if (t < 64) qrp_wave<32>(A1, pc, w, k);

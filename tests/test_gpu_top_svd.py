@@ -181,5 +181,19 @@ def test_invalid_arguments(ctx):
             ctx.top_svd(Cd, W, Rd, r)
     Wn = W.copy()
     Wn[2, 3] = np.nan
-    with pytest.raises(lra.LraError):
+    with pytest.raises(lra.LraError) as e:
         ctx.top_svd(Cd, Wn, Rd, 4)
+    assert e.value.args[0].endswith(f"({lra.ENONFINITE})")
+    # a NaN in C or an Inf in R: reported, outputs untouched
+    for bad in ("C", "R"):
+        C2, R2 = C.copy(), R.copy()
+        if bad == "C":
+            C2[57, 3] = np.nan
+        else:
+            R2[5, 80] = np.inf
+        Cb, Rb = _dev(C2, R2)
+        S0 = torch.full((4 * 100,), 7.0, dtype=torch.float64, device="cuda")
+        with pytest.raises(lra.LraError) as e:
+            ctx.top_svd(Cb, W, Rb, 4, S_out=S0)
+        assert e.value.args[0].endswith(f"({lra.ENONFINITE})")
+        assert bool((S0 == 7.0).all())
