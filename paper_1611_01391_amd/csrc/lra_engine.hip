@@ -1153,8 +1153,10 @@ DI Rows<T> slice_of(const TaskDesc& td, const Team& tm, int transpose, int64_t& 
     const int64_t r1 = rw.r0 + R < M ? rw.r0 + R : M;
     rw.nrows = r1 > rw.r0 ? (int)(r1 - rw.r0) : 0;
     if (LDSB) {
+        // an odd leading dimension: a column-parallel access (one row, many
+        // columns) spreads over the LDS banks
         rw.B = blds_ptr<T, KMAX>();
-        rw.ld = R;
+        rw.ld = R | 1;
     } else {
         rw.B = (T*)td.strip + rw.r0;
         rw.ld = M;
@@ -1364,8 +1366,15 @@ NOINL void basis_phase(const TaskDesc& td, Team& tio, int transpose, int started
     constexpr int LD = 2 * KMAX;
     T* AUG = (T*)sm.AUG;
     if (started) {
-        // W[d][c] = M^{-1}[c][d], in the right half of AUG
-        basis_product<T, KMAX>(rw, keff, AUG + KMAX, 1, LD);
+        // W[d][c] = M^{-1}[c][d] sits in the right half of AUG; a copy with c
+        // contiguous in the left half (free once the warm start is done)
+        // keeps the product's loads of W off a single LDS bank
+        for (int e = threadIdx.x; e < keff * keff; e += NT) {
+            const int d = e / keff, c = e - d * keff;
+            AUG[d * LD + c] = AUG[c * LD + KMAX + d];
+        }
+        __syncthreads();
+        basis_product<T, KMAX>(rw, keff, AUG, LD, 1);
     } else {
         // L1^{-1} by unit-triangular elimination on I, then L L1^{-1}
         for (int e = threadIdx.x; e < keff * keff; e += NT)
@@ -1584,7 +1593,7 @@ NOINL int swap_phase_bsel(const TaskDesc& td, Team& tio, int transpose, int keff
     int64_t* X = transpose ? sm.J : sm.I;
     int64_t R;
     const Rows<T> rw = slice_of<T, KMAX, true>(td, tm, transpose, R);
-    float* Bs = (float*)rw.B + R * KMAX;  // approximate C W, column-major, ld R
+    float* Bs = (float*)rw.B + rw.ld * KMAX;  // approximate C W, column-major, ld R
     constexpr int LD = 2 * KMAX;
     float* Wt = (float*)sm.AUG + KMAX;    // Wt[c * LD + a] = W[a][c]
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1759,7 +1768,7 @@ DI void maxvol_step(const TaskDesc& td, Team& tm, int transpose, int lds_b_bytes
     bool bsel = false;
     if constexpr (std::is_same<T, float>::value && KMAX <= 32 && LDSB) {
         const int64_t R = (M + tm.size - 1) / tm.size;
-        bsel = td.bf16_select != 0 && R <= NT && R * KMAX * 2 * (int64_t)sizeof(T) <= lds_b_bytes;
+        bsel = td.bf16_select != 0 && R <= NT && ((R | 1) + R) * KMAX * (int64_t)sizeof(T) <= lds_b_bytes;
     }
     trace_ev(tm, EV_STEP_BEGIN, transpose);
 
@@ -1841,7 +1850,7 @@ DI void maxvol_dispatch(const TaskDesc& td, Team& tm, int transpose, int lds_b_b
     const int64_t M = transpose ? td.n : td.m;
     const int64_t R = (M + tm.size - 1) / tm.size;
     trace_ev(tm, EV_DISPATCH, transpose);
-    if (R * sm.k * (int64_t)sizeof(T) <= lds_b_bytes) maxvol_step<T, KMAX, true>(td, tm, transpose, lds_b_bytes);
+    if ((R | 1) * sm.k * (int64_t)sizeof(T) <= lds_b_bytes) maxvol_step<T, KMAX, true>(td, tm, transpose, lds_b_bytes);
     else maxvol_step<T, KMAX, false>(td, tm, transpose, lds_b_bytes);
 }
 
@@ -2415,7 +2424,7 @@ NOINL void reduce_leader(const TaskDesc& td, Team& tio, int lds_b_bytes)
     }
     if (threadIdx.x < r) sm.J[threadIdx.x] = threadIdx.x;
     __syncthreads();
-    const bool lds = (int64_t)p * r * (int64_t)sizeof(T) <= lds_b_bytes;
+    const bool lds = (int64_t)(p | 1) * r * (int64_t)sizeof(T) <= lds_b_bytes;
     for (int it = 0; it < inner; ++it) {
         const int k_before = sm.k, had = sm.have_I;
         if (threadIdx.x < k_before) {

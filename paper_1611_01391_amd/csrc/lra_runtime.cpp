@@ -759,7 +759,8 @@ static lra_status plan_launch(lra_ctx* ctx, std::vector<Prob*>& probs, int prec6
     for (Prob* p : probs) {
         if (fixed_strip) continue;
         const int64_t R = (std::max(p->m, p->n) + p->team - 1) / p->team;
-        p->need_strip = R * p->kcap * (p->prec64 ? 8 : 4) > lp.lds_b[variant_index(p->prec64, p->kmx)];
+        // the engine's LDS slice has leading dimension R | 1
+        p->need_strip = (R | 1) * p->kcap * (p->prec64 ? 8 : 4) > lp.lds_b[variant_index(p->prec64, p->kmx)];
     }
     lp.pl = plan_teams(probs, lp.max_wgs);
     lp.grid = (int)lp.pl.wg_team.size();
