@@ -432,11 +432,17 @@ __global__ __launch_bounds__(256) void topsvd_core_kernel(const double* RC, cons
         return;
     }
     if (t == 0) out->tick[1] = wall_clock64();
-    // B = R_C[:r,:] W~ with W~[a][b] = W[pc[a]][pr[b]] (R_C upper triangular)
+    // W~[a][b] = W[pc[a]][pr[b]], staged in Y (free until the middle factor)
+    for (int e = t; e < k * k; e += 256) {
+        const int c = e / k, b = e - c * k;
+        Y[b * CORE_LD + c] = W[pc[c] * k + pr[b]];
+    }
+    __syncthreads();
+    // B = R_C[:r,:] W~ (R_C upper triangular)
     for (int e = t; e < r * k; e += 256) {
         const int b = e / r, a = e - b * r;
         double s = 0.0;
-        for (int c = a; c < k; ++c) s = fma(A1[c * CORE_LD + a], W[pc[c] * k + pr[b]], s);
+        for (int c = a; c < k; ++c) s = fma(A1[c * CORE_LD + a], Y[b * CORE_LD + c], s);
         B[b * CORE_LD + a] = s;
     }
     __syncthreads();
