@@ -493,6 +493,12 @@ def bench_cauchy(args):
                  "m": m, "n": m, "k0": 8, "k_max": 40, "tol": tol, "precision": args.precision})
     out["roofline"] = _alu_roofline(res.entries_read, kernel_ms,
                                     f"engine_kernel_cauchy_2p20_{'fp64' if f64 else 'fp32'}.md")
+    # the basis passes over the 2^20-row strips in HBM (counted by FETCH_SIZE / WRITE_SIZE)
+    tr = _profiled(f"engine_kernel_cauchy_2p20_{'fp64' if f64 else 'fp32'}.md", "traffic_bytes_per_launch")
+    if tr:
+        out["roofline"]["traffic"] = tr
+        out["roofline"]["traffic_GBps"] = tr / (kernel_ms * 1e-3) / 1e9
+        out["roofline"]["traffic_frac_hbm"] = out["roofline"]["traffic_GBps"] / HBM_PEAK_GBS
     out["cpu_baseline"] = cpu
     out["result"] = {"status": int(res.status), "k": int(res.k), "sweeps": int(res.sweeps_done),
                      "swaps": int(res.swaps_total), "est_rel": res.err_est_rel,
