@@ -472,7 +472,15 @@ def bench_cauchy(args):
     ctx = lra.Context()
     src = lra.cauchy(torch.from_numpy(s).cuda(), torch.from_numpy(t).cuda())
     kw = dict(init_cols=d.cand_cols, sample_rows=d.sample_rows, sample_cols=d.sample_cols, k_max=40,
-              precision=lra.PREC_FP64 if f64 else lra.PREC_MIXED, raise_on_error=False)
+              precision=lra.PREC_FP64 if f64 else lra.PREC_MIXED, raise_on_error=False, team_wgs=args.team)
+    tuned = None
+    if args.autotune and not args.team:
+        team, tms = ctx.autotune_team(src, 8, 4, tol, init_cols=d.cand_cols, sample_rows=d.sample_rows,
+                                      sample_cols=d.sample_cols, k_max=40,
+                                      precision=lra.PREC_FP64 if f64 else lra.PREC_MIXED)
+        tuned = {"team_wgs": team, "kernel_ms": tms}
+        kw["team_wgs"] = team
+        log(f"# autotuned team: {team} workgroups ({tms:.3f} ms)")
     el, st, res = _timed_steps(ctx, torch, lambda: ctx.ca_cur(src, 8, 4, tol, **kw), args.steps, args.warmup)
     kernel_ms = st["engine_ms_total"] / max(1, st["launches"])
     log(f"# gpu: status {res.status} k {res.k} sweeps {res.sweeps_done} swaps {res.swaps_total} "
@@ -490,7 +498,8 @@ def bench_cauchy(args):
     out = _base(args, args.steps / el, "CUR LRAs/s", el * 1e3 / args.steps, "f64" if f64 else "f32",
                 {"workload": f"implicit Cauchy 1/(s_i - t_j), s ~ U[0,1], t ~ U[2,3], m = n = 2^20, adaptive k "
                              f"8..40 step 8, tol {tol:g}, up to 4 sweeps per rank",
-                 "m": m, "n": m, "k0": 8, "k_max": 40, "tol": tol, "precision": args.precision})
+                 "m": m, "n": m, "k0": 8, "k_max": 40, "tol": tol, "precision": args.precision,
+                 "autotuned": tuned})
     out["roofline"] = _alu_roofline(res.entries_read, kernel_ms,
                                     f"engine_kernel_cauchy_2p20_{'fp64' if f64 else 'fp32'}.md")
     # the basis passes over the 2^20-row strips in HBM (counted by FETCH_SIZE / WRITE_SIZE)
