@@ -171,6 +171,45 @@ def test_after_ca_cur_dense_16384(ctx, precision):
     np.testing.assert_allclose(lra_v, cur_v, rtol=0, atol=1e-9 * np.abs(A).max())
 
 
+def test_strided_factors_and_outputs(ctx):
+    """Leading dimensions above the row counts, through the C ABI: C inside a
+    taller column-major buffer (ldc = m + 7), R inside a wider row-major one
+    (ldr = n + 5), S and T^T written with padding (lds = m + 3, ldt = n + 9):
+    the same bits as the packed call, and the padding untouched."""
+    from paper_1611_01391_amd import lra
+    _say("top svd strided")
+    m, n, k, r = 1200, 900, 16, 10
+    Cm, W, Rm = _factors(9, m, n, k, scales=3.0)
+    Cd, Rd = _dev(Cm, Rm)
+    S0, sg0, T0, pc0, pr0 = ctx.top_svd(Cd, W, Rd, r)
+    ldc, ldr, lds, ldt = m + 7, n + 5, m + 3, n + 9
+    Cbig = torch.zeros(k, ldc, dtype=torch.float64, device="cuda")
+    Cbig[:, :m] = torch.from_numpy(np.ascontiguousarray(Cm.T)).cuda()
+    Rbig = torch.zeros(k, ldr, dtype=torch.float64, device="cuda")
+    Rbig[:, :n] = torch.from_numpy(Rm).cuda()
+    Sb = torch.full((r, lds), 5.0, dtype=torch.float64, device="cuda")
+    Tb = torch.full((r, ldt), 5.0, dtype=torch.float64, device="cuda")
+    Wh = np.ascontiguousarray(W)
+    sg = np.zeros(r)
+    pc = np.zeros(k, dtype=np.int64)
+    pr = np.zeros(k, dtype=np.int64)
+    torch.cuda.synchronize()
+    st = lra.lib().lra_top_svd(ctx._h, m, n, k, r, lra.F64, Cbig.data_ptr(), ldc, Wh.ctypes.data, Rbig.data_ptr(),
+                               ldr, Sb.data_ptr(), lds, sg.ctypes.data, Tb.data_ptr(), ldt, pc.ctypes.data,
+                               pr.ctypes.data)
+    assert st == 0, st
+    np.testing.assert_array_equal(sg, sg0)
+    np.testing.assert_array_equal(pc, pc0)
+    np.testing.assert_array_equal(pr, pr0)
+    np.testing.assert_array_equal(Sb[:, :m].cpu().numpy(), S0.t().cpu().numpy())
+    np.testing.assert_array_equal(Tb[:, :n].cpu().numpy(), T0.cpu().numpy())
+    assert bool((Sb[:, m:] == 5.0).all()) and bool((Tb[:, n:] == 5.0).all())
+    # leading dimensions below the row counts are rejected
+    st = lra.lib().lra_top_svd(ctx._h, m, n, k, r, lra.F64, Cbig.data_ptr(), m - 1, Wh.ctypes.data, Rbig.data_ptr(),
+                               ldr, Sb.data_ptr(), lds, sg.ctypes.data, Tb.data_ptr(), ldt, None, None)
+    assert st == lra.EINVAL
+
+
 def test_invalid_arguments(ctx):
     from paper_1611_01391_amd import lra
     _say("top svd invalid arguments")
