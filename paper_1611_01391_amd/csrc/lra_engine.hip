@@ -394,39 +394,51 @@ DI void team_barrier(Team& tm)
 }
 
 // Team-wide argmax: publish this workgroup's best key and its candidate row
-// (sm.pay[0..n)) in its own slot, stamped with the exchange number; thread i
-// of every workgroup waits for slot i's stamp, so no counter is contended.
-// Then every workgroup reduces all slots and loads the winning row (owner =
-// row / rows_per_wg) into sm.pay.  Slots alternate between two banks: a
-// workgroup can only publish exchange x + 1 after every slot of exchange x
-// arrived, i.e. after every workgroup finished reading exchange x - 1.  With
-// one workgroup the local result is final.
+// (sm.pay[0..n)) in its own slot; thread i of every workgroup waits for slot
+// i, so no counter is contended.  Then every workgroup reduces all slots and
+// loads the winning row (owner = row / rows_per_wg) into sm.pay.  Slots
+// alternate between two banks: a workgroup can only publish exchange x + 1
+// after every slot of exchange x arrived, i.e. after every workgroup finished
+// reading exchange x - 1.  With one workgroup the local result is final.
+//
+// The key words carry the exchange's version in their top bit, which a key
+// does not use (hi holds the bits of a modulus, sign 0; lo the complement of
+// row << 8 | col, top bit 1, or 0 for "no candidate"): version 1 for
+// exchanges 0 and 1, then alternating per use of a bank, so the zeroed
+// control block and the bank's previous exchange both read as not arrived.
+// The writer orders its row before the key words with one release fence; a
+// reader that sees both words at the current version has the key in hand
+// (no second round trip for it), and its acquire fence makes the row visible.
 template <typename T, int KMAX>
 DI K2 team_argmax(Team& tm, Smem<T, KMAX>& sm, const K2& mine, int n, int64_t rows_per_wg)
 {
     if (tm.size == 1) return mine;
     const int par = tm.xepoch & 1;
-    const uint32_t stamp = tm.xepoch + 1;
-    tm.xepoch = stamp;
+    constexpr uint64_t TOP = 1ull << 63;
+    const uint64_t ver = ((uint64_t)(((tm.xepoch >> 1) & 1u) ^ 1u)) << 63;
+    tm.xepoch++;
     GL uint8_t* my = slot_ptr(tm, par, tm.rank);
     GL double* mypay = (GL double*)(my + 32);
-    // written by wavefront 0 only: its release below orders all of them
+    // written by wavefront 0 only: the release fence below orders all of them
     if (threadIdx.x < n)
         __hip_atomic_store(mypay + threadIdx.x, (double)sm.pay[threadIdx.x], __ATOMIC_RELAXED, AGENT);
     if (threadIdx.x == 0) {
-        __hip_atomic_store((GL uint64_t*)my, mine.hi, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store((GL uint64_t*)(my + 8), mine.lo, __ATOMIC_RELAXED, AGENT);
-        __hip_atomic_store((GL uint32_t*)(my + 16), stamp, __ATOMIC_RELEASE, AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store((GL uint64_t*)my, mine.hi | ver, __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store((GL uint64_t*)(my + 8), (mine.lo & ~TOP) | ver, __ATOMIC_RELAXED, AGENT);
     }
     // a slot that never arrives yields the reserved key K2_FAIL, which wins
     // the reduction (keys of moduli, +inf included, have smaller hi words)
     K2 o = k2_none();
     if (threadIdx.x < tm.size) {
-        const GL uint8_t* sp = slot_ptr(tm, par, threadIdx.x);
+        const GL uint64_t* sp = (const GL uint64_t*)slot_ptr(tm, par, threadIdx.x);
         const int64_t t0 = wall_clock64();
         bool bad = false;
-        for (uint32_t spins = 1; __hip_atomic_load((const GL uint32_t*)(sp + 16), __ATOMIC_RELAXED, AGENT) != stamp;
-             ++spins) {
+        uint64_t h, l;
+        for (uint32_t spins = 1;; ++spins) {
+            h = __hip_atomic_load(sp, __ATOMIC_RELAXED, AGENT);
+            l = __hip_atomic_load(sp + 1, __ATOMIC_RELAXED, AGENT);
+            if ((h & TOP) == ver && (l & TOP) == ver) break;
             __builtin_amdgcn_s_sleep(1);
             if ((spins & 63) == 0 && wall_clock64() - t0 > tm.timeout) {
                 __hip_atomic_fetch_or(gl(tm.err), 1u, __ATOMIC_RELAXED, AGENT);
@@ -438,8 +450,8 @@ DI K2 team_argmax(Team& tm, Smem<T, KMAX>& sm, const K2& mine, int n, int64_t ro
         if (bad) {
             o = K2{~0ull, ~0ull};
         } else {
-            o.hi = __hip_atomic_load((const GL uint64_t*)sp, __ATOMIC_RELAXED, AGENT);
-            o.lo = __hip_atomic_load((const GL uint64_t*)(sp + 8), __ATOMIC_RELAXED, AGENT);
+            o.hi = h & ~TOP;
+            o.lo = (l & ~TOP) ? (l | TOP) : 0ull;
         }
     }
     const K2 best = block_argmax(o, sm, tm);
@@ -448,8 +460,10 @@ DI K2 team_argmax(Team& tm, Smem<T, KMAX>& sm, const K2& mine, int n, int64_t ro
         return k2_none();
     }
     if (n > 0) {
-        const int w = (int)(k2_row(best) / rows_per_wg);
-        if (threadIdx.x < n) {
+        // no candidate anywhere (key 0): the callers stop without reading a row
+        if (best.lo != 0ull && threadIdx.x < n) {
+            const int64_t wo = k2_row(best) / rows_per_wg;
+            const int w = wo < tm.size ? (int)wo : tm.size - 1;
             const GL double* wp = (const GL double*)(slot_ptr(tm, par, w) + 32);
             sm.pay[threadIdx.x] = (T)__hip_atomic_load(wp + threadIdx.x, __ATOMIC_RELAXED, AGENT);
         }

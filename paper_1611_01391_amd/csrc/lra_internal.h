@@ -118,7 +118,7 @@ enum TraceEv : int32_t {
 // (two int32 by barrier parity); slots start at CTL_HDR, two banks (barrier
 // parity) of `team size` slots of SLOT_STRIDE bytes.
 constexpr int CTL_HDR = 256;
-constexpr int SLOT_STRIDE = 544;  // 32-byte key + 64 binary64 payload
+constexpr int SLOT_STRIDE = 544;  // 32-byte header (two key words) + 64 binary64 payload
 constexpr int KMAX_ALL = 64;
 constexpr int NT = 256;           // threads per workgroup
 
