@@ -409,10 +409,35 @@ DI void team_barrier(Team& tm)
 // The writer orders its row before the key words with one release fence; a
 // reader that sees both words at the current version has the key in hand
 // (no second round trip for it), and its acquire fence makes the row visible.
-template <typename T, int KMAX>
-DI K2 team_argmax(Team& tm, Smem<T, KMAX>& sm, const K2& mine, int n, int64_t rows_per_wg)
+// Work that needs no exchange result can run while the slots travel: an
+// optional hook (every thread, after this workgroup has published) and an
+// optional LDS row to publish instead of sm.pay.
+struct NoHook {
+    static constexpr bool active = false;
+    DI void operator()() const {}
+};
+
+template <typename F>
+struct Hook {
+    static constexpr bool active = true;
+    F f;
+    DI void operator()() const { f(); }
+};
+
+template <typename F>
+DI Hook<F> make_hook(F f) { return Hook<F>{f}; }
+
+template <typename T, int KMAX, typename H = NoHook>
+DI K2 team_argmax(Team& tm, Smem<T, KMAX>& sm, const K2& mine, int n, int64_t rows_per_wg, const H& hook = H(),
+                  const double* cand = nullptr)
 {
-    if (tm.size == 1) return mine;
+    if (tm.size == 1) {
+        if constexpr (H::active) {
+            hook();
+            __syncthreads();
+        }
+        return mine;
+    }
     const int par = tm.xepoch & 1;
     constexpr uint64_t TOP = 1ull << 63;
     const uint64_t ver = ((uint64_t)(((tm.xepoch >> 1) & 1u) ^ 1u)) << 63;
@@ -421,12 +446,14 @@ DI K2 team_argmax(Team& tm, Smem<T, KMAX>& sm, const K2& mine, int n, int64_t ro
     GL double* mypay = (GL double*)(my + 32);
     // written by wavefront 0 only: the release fence below orders all of them
     if (threadIdx.x < n)
-        __hip_atomic_store(mypay + threadIdx.x, (double)sm.pay[threadIdx.x], __ATOMIC_RELAXED, AGENT);
+        __hip_atomic_store(mypay + threadIdx.x, cand ? cand[threadIdx.x] : (double)sm.pay[threadIdx.x], __ATOMIC_RELAXED,
+                           AGENT);
     if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_store((GL uint64_t*)my, mine.hi | ver, __ATOMIC_RELAXED, AGENT);
         __hip_atomic_store((GL uint64_t*)(my + 8), (mine.lo & ~TOP) | ver, __ATOMIC_RELAXED, AGENT);
     }
+    if constexpr (H::active) hook();
     // a slot that never arrives yields the reserved key K2_FAIL, which wins
     // the reduction (keys of moduli, +inf included, have smaller hi words)
     K2 o = k2_none();
@@ -1454,16 +1481,40 @@ NOINL int swap_phase(const TaskDesc& td, Team& tio, int transpose, int keff, int
             if (a > bv) { bv = a; bc = c; }
         }
         if (!has) bv = -1.0;
+        // the last swap's update of W^T is applied while the next exchange's
+        // slots travel (it is needed only once the exchange has returned)
+        bool wpend = false;
+        const auto wupdate = make_hook([&]() {
+            if (wpend)
+                for (int e = threadIdx.x; e < keff * keff; e += NT) {
+                    const int c = e / keff, d = e % keff;
+                    Wr[c * LDW + d] -= (T)sm.lumul[0][d] * sm.g[c];
+                }
+        });
+        const int wave = threadIdx.x >> 6;
         for (;;) {
             const K2 kl = bv >= 0.0 ? k2_make(bv, myrow, bc) : k2_none();
-            const K2 wb = block_argmax(kl, sm, tm);
-            trace_ev(tm, EV_SWAP_RED, 0);
-            if (has && k2_row(wb) == myrow) {
+            // each wavefront's best row goes to LDS before the workgroup
+            // reduction's barrier, so the winner's row is in place after it
+            const K2 ww = wave_argmax(kl);
+            if (has && ww.lo != 0ull && k2_row(ww) == myrow) {
 #pragma unroll
-                for (int c = 0; c < KMAX; ++c) sm.pay[c] = row[c];
+                for (int c = 0; c < KMAX; ++c) sm.lucol[wave][c] = (double)row[c];
             }
+            if ((threadIdx.x & 63) == 0) sm.kred[tm.tog][wave] = ww;
             __syncthreads();
-            const K2 wv = team_argmax(tm, sm, wb, keff, R);
+            K2 wb = sm.kred[tm.tog][0];
+            int wbw = 0;
+#pragma unroll
+            for (int i = 1; i < NWAVE; ++i)
+                if (k2_better(sm.kred[tm.tog][i], wb)) {
+                    wb = sm.kred[tm.tog][i];
+                    wbw = i;
+                }
+            tm.tog ^= 1;
+            trace_ev(tm, EV_SWAP_RED, 0);
+            const K2 wv = team_argmax(tm, sm, wb, keff, R, wupdate, sm.lucol[wbw]);
+            wpend = false;
             if (tm.failed) { tio = tm; return -1; }
             trace_ev(tm, EV_SWAP_XCH, 0);
             if (!(k2_val(wv) > lim)) break;
@@ -1474,16 +1525,17 @@ NOINL int swap_phase(const TaskDesc& td, Team& tio, int transpose, int keff, int
             const int js = k2_col(wv);
             const int64_t is = k2_row(wv);
             if (threadIdx.x < keff) {
-                sm.g[threadIdx.x] = (sm.pay[threadIdx.x] - (T)(threadIdx.x == js ? 1 : 0)) / sm.pay[js];
+                // the winning row: from the exchange, or this workgroup's own
+                // when it is the whole team
+                const bool own = tm.size == 1;
+                const T pc = own ? (T)sm.lucol[wbw][threadIdx.x] : sm.pay[threadIdx.x];
+                const T pj = own ? (T)sm.lucol[wbw][js] : sm.pay[js];
+                sm.g[threadIdx.x] = (pc - (T)(threadIdx.x == js ? 1 : 0)) / pj;
                 if (wmaint) sm.lumul[0][threadIdx.x] = (double)Wr[js * LDW + threadIdx.x];
             }
             if (threadIdx.x == 0) X[js] = is;
             __syncthreads();
-            if (wmaint)
-                for (int e = threadIdx.x; e < keff * keff; e += NT) {
-                    const int c = e / keff, d = e % keff;
-                    Wr[c * LDW + d] -= (T)sm.lumul[0][d] * sm.g[c];
-                }
+            wpend = wmaint != 0;
             ++swaps;
             trace_ev(tm, EV_SWAP, swaps);
             T gv[KMAX];

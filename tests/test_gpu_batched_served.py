@@ -194,6 +194,26 @@ def test_batched_equals_single(ctx):
         _same(out[b], one, f"block {b}")
 
 
+def test_batched_repeatable(ctx):
+    """The same batched launch three times: every block bit-identical.  Team
+    exchanges carry data between workgroups on several XCDs; a protocol that
+    could hand a reader a stale slot shows up here as blocks that differ from
+    run to run (the oracle comparison alone would pass many of them, since
+    most far-field blocks have several valid results)."""
+    lra = _lra()
+    _say("batched repeatable")
+    x, blocks = _multipole_case(1 << 16, 512)
+    xd = torch.from_numpy(x).cuda()
+    runs = []
+    for _ in range(3):
+        jobs = [(lra.invdist(xd[a0:a1], xd[b0:b1]), 8, 4, 1e-8) for (a0, a1, b0, b1) in blocks]
+        _, out = ctx.ca_cur_batched(jobs, raise_on_error=False, k_max=48)
+        runs.append(out)
+    for b in range(len(blocks)):
+        _same(runs[0][b], runs[1][b], f"block {b}, runs 0/1")
+        _same(runs[0][b], runs[2][b], f"block {b}, runs 0/2")
+
+
 def test_batched_mixed_precision_and_fixed_k(ctx):
     lra = _lra()
     _say("batched mixed / fixed k")
