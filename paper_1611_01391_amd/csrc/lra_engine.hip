@@ -1348,7 +1348,9 @@ NOINL int gepp_phase(const TaskDesc& td, Team& tio, int transpose, double thresh
         if (threadIdx.x < k && wr >= rw.r0 && wr < rend) sm.pay[threadIdx.x] = rw.B[threadIdx.x * rw.ld + (wr - rw.r0)];
         const K2 wv = team_argmax(tm, sm, wb, k, R);
         if (tm.failed) { tio = tm; return -1; }
-        __syncthreads();
+        // a team exchange ends with a barrier after the winning row; alone,
+        // the row written above must reach every wavefront
+        if (tm.size == 1) __syncthreads();
         const double pav = k2_val(wv);
         if (pav == 0.0 && t == 0) {  // a zero strip: no pivot at all
             if (threadIdx.x == 0) { sm.status = -2; sm.phase = PH_DONE; }
@@ -1386,8 +1388,9 @@ NOINL int gepp_phase(const TaskDesc& td, Team& tio, int transpose, double thresh
                 }
             });
         }
+        // no barrier here: the next reduction's barrier orders these updates
+        // before the next pivot row is read and sm.pay is rewritten
         kl = bv >= 0.0 ? k2_make(bv, rw.r0 + br, 0) : k2_none();
-        __syncthreads();
     }
     tio = tm;
     return keff;
