@@ -533,6 +533,34 @@ DI double store_chunk(const T* v, int c0, int k, const Rows<T>& rw, int r, doubl
     return lmax;
 }
 
+// Dense sources, CH columns of a row loaded together (the chunk width is
+// chosen from k, so that a small rank issues no loads for columns it lacks).
+template <typename T, int CH>
+DI double gather_dense_rows(const DevSource& s, int transpose, const int64_t* F, int k, const Rows<T>& rw, int tid,
+                            int nth)
+{
+    double lmax = 0.0;
+    for (int r = tid; r < rw.nrows; r += nth) {
+        const int64_t gi = rw.r0 + r;
+        for (int c0 = 0; c0 < k; c0 += CH) {
+            int64_t ri[CH], cj[CH];
+            T v[CH];
+#pragma unroll
+            for (int cc = 0; cc < CH; ++cc) {
+                const int c = c0 + cc < k ? c0 + cc : c0;
+                ri[cc] = transpose ? F[c] : gi;
+                cj[cc] = transpose ? gi : F[c];
+            }
+            if (s.dtype == 0)
+                entries_e<float, T, CH>(s, ri, cj, v);
+            else
+                entries_e<double, T, CH>(s, ri, cj, v);
+            lmax = store_chunk<T, CH>(v, c0, k, rw, r, lmax);
+        }
+    }
+    return lmax;
+}
+
 template <typename T, int KMAX>
 DI double gather_rows(const DevSource& src, int transpose, const Smem<T, KMAX>& sm, const int64_t* F, int k,
                       const Rows<T>& rw, int tid, int nth)
@@ -540,25 +568,13 @@ DI double gather_rows(const DevSource& src, int transpose, const Smem<T, KMAX>& 
     const DevSource s = src;  // read once: stores to a global strip could alias it
     double lmax = 0.0;
     if (s.kind == 0 || s.kind == 3) {
-        constexpr int CH = KMAX < 32 ? KMAX : 32;
-        for (int r = tid; r < rw.nrows; r += nth) {
-            const int64_t gi = rw.r0 + r;
-            for (int c0 = 0; c0 < k; c0 += CH) {
-                int64_t ri[CH], cj[CH];
-                T v[CH];
-#pragma unroll
-                for (int cc = 0; cc < CH; ++cc) {
-                    const int c = c0 + cc < k ? c0 + cc : c0;
-                    ri[cc] = transpose ? F[c] : gi;
-                    cj[cc] = transpose ? gi : F[c];
-                }
-                if (s.dtype == 0)
-                    entries_e<float, T, CH>(s, ri, cj, v);
-                else
-                    entries_e<double, T, CH>(s, ri, cj, v);
-                lmax = store_chunk<T, CH>(v, c0, k, rw, r, lmax);
-            }
-        }
+        constexpr int C16 = KMAX < 16 ? KMAX : 16, C32 = KMAX < 32 ? KMAX : 32;
+        if (k <= 8)
+            lmax = gather_dense_rows<T, 8>(s, transpose, F, k, rw, tid, nth);
+        else if (k <= C16)
+            lmax = gather_dense_rows<T, C16>(s, transpose, F, k, rw, tid, nth);
+        else
+            lmax = gather_dense_rows<T, C32>(s, transpose, F, k, rw, tid, nth);
     } else {
         constexpr int CH = 8;
         for (int r = tid; r < rw.nrows; r += nth) {
@@ -1077,12 +1093,14 @@ struct Acc4<float> {
     static DI int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T, int KMAX>
-DI void basis_product(const Rows<T>& rw, int kd, const T* W, int wsd, int wsc)
+// KD: the widest kd this instance serves; smaller ranks run the instance of
+// their own width, so that no load is issued for steps beyond kd.
+template <typename T, int KD>
+DI void basis_product_k(const Rows<T>& rw, int kd, const T* W, int wsd, int wsc)
 {
     typedef typename Acc4<T>::type acc_t;
-    constexpr int KB = KMAX / 4;
-    constexpr int CT = (KMAX + 15) / 16;
+    constexpr int KB = KD / 4;
+    constexpr int CT = (KD + 15) / 16;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int ntiles = (rw.nrows + 15) / 16;
     // only the 4-deep steps and 16-wide column tiles that k reaches
@@ -1143,6 +1161,20 @@ DI void basis_product(const Rows<T>& rw, int kd, const T* W, int wsd, int wsc)
             }
         }
     }
+}
+
+template <typename T, int KMAX>
+DI void basis_product(const Rows<T>& rw, int kd, const T* W, int wsd, int wsc)
+{
+    constexpr int K16 = KMAX < 16 ? KMAX : 16, K32 = KMAX < 32 ? KMAX : 32;
+    if (kd <= 8)
+        basis_product_k<T, 8>(rw, kd, W, wsd, wsc);
+    else if (kd <= K16)
+        basis_product_k<T, K16>(rw, kd, W, wsd, wsc);
+    else if (kd <= K32)
+        basis_product_k<T, K32>(rw, kd, W, wsd, wsc);
+    else
+        basis_product_k<T, KMAX>(rw, kd, W, wsd, wsc);
 }
 
 // ----------------------------------------------------------------------------
