@@ -1248,20 +1248,26 @@ DI void warm_load(const TaskDesc& td, Smem<T, KMAX>& sm, int transpose, bool kee
     const int64_t* X = transpose ? sm.J : sm.I;
     constexpr int LD = 2 * KMAX;
     T* AUG = (T*)sm.AUG;
-    // M[c][s] = strip(X[s], c)
+    // M[c][s] = strip(X[s], c); batches as wide as k^2 needs (a small rank in
+    // a wide variant would otherwise read or generate mostly repeated entries)
     const int kk = k * k;
-    load_entries<T, (KMAX * KMAX + NT - 1) / NT>(
-        td.src, kk, threadIdx.x, NT,
-        [&](int e, int64_t& i, int64_t& j) {
-            const int c = e / k, s2 = e % k;
-            i = transpose ? F[c] : X[s2];
-            j = transpose ? X[s2] : F[c];
-        },
-        [&](int e, T v) {
-            const int c = e / k, s2 = e % k;
-            AUG[c * LD + s2] = v;
-            if (!keep_right) AUG[c * LD + KMAX + s2] = (T)(c == s2 ? 1 : 0);
-        });
+    const auto idx = [&](int e, int64_t& i, int64_t& j) {
+        const int c = e / k, s2 = e % k;
+        i = transpose ? F[c] : X[s2];
+        j = transpose ? X[s2] : F[c];
+    };
+    const auto st = [&](int e, T v) {
+        const int c = e / k, s2 = e % k;
+        AUG[c * LD + s2] = v;
+        if (!keep_right) AUG[c * LD + KMAX + s2] = (T)(c == s2 ? 1 : 0);
+    };
+    constexpr int PBF = (KMAX * KMAX + NT - 1) / NT, PB4 = PBF < 4 ? PBF : 4;
+    if (kk <= NT)
+        load_entries<T, 1>(td.src, kk, threadIdx.x, NT, idx, st);
+    else if (kk <= PB4 * NT)
+        load_entries<T, PB4>(td.src, kk, threadIdx.x, NT, idx, st);
+    else
+        load_entries<T, PBF>(td.src, kk, threadIdx.x, NT, idx, st);
 }
 
 // Warm start from the last step's inverse (binary64): that step ended with
