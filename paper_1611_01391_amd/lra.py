@@ -78,6 +78,28 @@ class Block(C.Structure):
                 ("sweeps", C.c_int32), ("tol", C.c_double)]
 
 
+_BLOCK_DT = np.dtype(Block)
+_RESULT_DT = np.dtype(ResultC)
+_SOURCE_DT = np.dtype(Source)
+
+
+def _block_array(blocks):
+    """The C array of lra_block for a sequence of (DeviceSource, k, sweeps,
+    tol), filled a field at a time over all blocks (thousands of far-field
+    blocks per call: per-element ctypes assignments cost milliseconds)."""
+    nb = len(blocks)
+    arr = (Block * max(1, nb))()
+    if nb:
+        a = np.frombuffer(arr, dtype=_BLOCK_DT)
+        a["src"] = np.frombuffer(b"".join([bytes(b[0].struct) for b in blocks]), dtype=_SOURCE_DT)
+        a["m"] = [b[0].m for b in blocks]
+        a["n"] = [b[0].n for b in blocks]
+        a["k"] = [int(b[1]) for b in blocks]
+        a["sweeps"] = [int(b[2]) for b in blocks]
+        a["tol"] = [float(b[3]) for b in blocks]
+    return arr
+
+
 class RequestC(C.Structure):
     _fields_ = [("src", Source), ("m", C.c_int64), ("n", C.c_int64), ("k", C.c_int32),
                 ("sweeps", C.c_int32), ("tol", C.c_double), ("opts", Options),
@@ -492,14 +514,7 @@ class Context:
         """Time planning floors for shared launches; returns (floor_rows, ms)."""
         o = default_options(**opts)
         nb = len(blocks)
-        arr = (Block * max(1, nb))()
-        for b, (src, k, sweeps, tol) in enumerate(blocks):
-            arr[b].src = src.struct
-            arr[b].m = src.m
-            arr[b].n = src.n
-            arr[b].k = int(k)
-            arr[b].sweeps = int(sweeps)
-            arr[b].tol = float(tol)
+        arr = _block_array(blocks)
         fl = C.c_int64(0)
         ms = C.c_double(0.0)
         st = lib().lra_autotune_batched(self._h, arr, nb, C.byref(o), C.byref(fl), C.byref(ms))
@@ -524,43 +539,36 @@ class Context:
         blocks are views into shared buffers."""
         o = default_options(**opts)
         nb = len(blocks)
-        arr = (Block * max(1, nb))()
-        kcaps = np.empty(max(1, nb), dtype=np.int64)
-        for b, (src, k, sweeps, tol) in enumerate(blocks):
-            arr[b].src = src.struct
-            arr[b].m = src.m
-            arr[b].n = src.n
-            arr[b].k = int(k)
-            arr[b].sweeps = int(sweeps)
-            arr[b].tol = float(tol)
-            kcaps[b] = max(int(k), o.k_max)
+        arr = _block_array(blocks)
+        kcaps = np.maximum(np.frombuffer(arr, dtype=_BLOCK_DT)["k"][:nb].astype(np.int64), o.k_max)
         off = np.zeros(max(1, nb) + 1, dtype=np.int64)
         off2 = np.zeros(max(1, nb) + 1, dtype=np.int64)
-        np.cumsum(kcaps[:nb], out=off[1:nb + 1])
-        np.cumsum(kcaps[:nb] * kcaps[:nb], out=off2[1:nb + 1])
+        np.cumsum(kcaps, out=off[1:nb + 1])
+        np.cumsum(kcaps * kcaps, out=off2[1:nb + 1])
         I = np.zeros(max(1, off[nb]), dtype=np.int64)
         J = np.zeros(max(1, off[nb]), dtype=np.int64)
         G = np.zeros(max(1, off2[nb]))
         U = np.zeros(max(1, off2[nb]))
+        # the result records, filled field by field over all blocks at once
         res_arr = (ResultC * max(1, nb))()
-        for b in range(nb):
-            r = res_arr[b]
-            r.I = I.ctypes.data + 8 * int(off[b])
-            r.J = J.ctypes.data + 8 * int(off[b])
-            r.G = G.ctypes.data + 8 * int(off2[b])
-            r.U = U.ctypes.data + 8 * int(off2[b])
+        rv = np.frombuffer(res_arr, dtype=_RESULT_DT)[:nb]
+        rv["I"] = I.ctypes.data + 8 * off[:nb]
+        rv["J"] = J.ctypes.data + 8 * off[:nb]
+        rv["G"] = G.ctypes.data + 8 * off2[:nb]
+        rv["U"] = U.ctypes.data + 8 * off2[:nb]
         st = lib().lra_ca_cur_batched(self._h, arr, nb, C.byref(o), res_arr)
         if st < 0 and raise_on_error and st not in (ERANK, ENONFINITE):
             raise LraError(st, "lra_ca_cur_batched")
+        ks = np.maximum(rv["k"], 0).tolist()
+        i0s, g0s = off[:nb].tolist(), off2[:nb].tolist()
+        f = [rv[name].tolist() for name in ("status", "sweeps_done", "swaps_total", "entries_read", "err_est_rel",
+                                            "err_est_abs", "err_mean", "err_var", "nucleus_cond1")]
         out = []
         for b in range(nb):
-            r = res_arr[b]
-            k = max(0, r.k)
-            i0, g0 = int(off[b]), int(off2[b])
-            out.append(Result(r.status, k, I[i0:i0 + k], J[i0:i0 + k],
+            k, i0, g0 = ks[b], i0s[b], g0s[b]
+            out.append(Result(f[0][b], k, I[i0:i0 + k], J[i0:i0 + k],
                               G[g0:g0 + k * k].reshape(k, k), U[g0:g0 + k * k].reshape(k, k),
-                              r.sweeps_done, r.swaps_total, r.entries_read, r.err_est_rel,
-                              r.err_est_abs, r.err_mean, r.err_var, r.nucleus_cond1))
+                              f[1][b], f[2][b], f[3][b], f[4][b], f[5][b], f[6][b], f[7][b], f[8][b]))
         return st, out
 
     # -- serving ----------------------------------------------------------
