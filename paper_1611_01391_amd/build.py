@@ -36,7 +36,8 @@ def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
-    for src, dev in (("lra_engine.hip", True), ("lra_topsvd.hip", True), ("lra_runtime.cpp", False)):
+    for src, dev in (("lra_engine.hip", True), ("lra_topsvd.hip", True), ("lra_pack.hip", True),
+                     ("lra_runtime.cpp", False)):
         obj = os.path.join(objdir, src + ".o")
         cmd = [HIPCC, "--offload-arch=" + ARCH] + COMMON + (DEVICE_FLAGS if dev else []) + \
               ["-c", os.path.join(CSRC, src), "-o", obj]

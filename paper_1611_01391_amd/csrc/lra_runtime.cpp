@@ -15,6 +15,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/lra.h"
@@ -26,6 +27,8 @@ const void* engine_kernel_ptr(int prec64, int kmax);
 hipError_t launch_engine(int prec64, int kmax, int grid, size_t smem, bool cooperative,
                          const EngineArgs& ea, hipStream_t stream);
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t stream);
+hipError_t launch_pack_factors(const void* base, const int64_t* off, int np, double* out_g, double* out_u,
+                               hipStream_t stream);
 hipError_t launch_factors(const DevSource& src, int64_t m, int64_t n, int k, const int64_t* I, const int64_t* J,
                           int out64, void* C, void* R, hipStream_t stream);
 hipError_t noalloc_scratch_init(int device);
@@ -944,9 +947,11 @@ static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, 
         p.kmx = kmax_bucket(kcap_all);
         pp.push_back(&p);
     }
+    const double t_plan0 = now_us();
     LaunchPlan lp;
     lra_status rs = plan_launch(ctx, pp, prec64, kmax_bucket(kcap_all), false, lp);
     if (rs != LRA_OK) return rs;
+    const double t_plan1 = now_us();
     bool want_G = false, want_U = false;
     for (size_t i = 0; i < np; ++i) {
         want_G = want_G || res[i]->G;
@@ -962,6 +967,12 @@ static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, 
         regs[i].Q = L.add(8 * (int64_t)probs[i].q, 8);
         regs[i].S = L.add(8 * (int64_t)probs[i].s, 8);
     }
+    // many problems with G or U wanted: their k x k factors are packed on the
+    // device and only sum k^2 entries read back (not the kcap^2 regions)
+    int64_t kk_all = 0;
+    for (size_t i = 0; i < np; ++i) kk_all += (int64_t)probs[i].kcap * probs[i].kcap;
+    bool pack = !fixed && (want_G || want_U) && np >= 32;
+    const int64_t off_pack = pack ? L.add(24 * (int64_t)np, 8) : -1;
     const int64_t rb0 = L.add(0);
     for (size_t i = 0; i < np; ++i) regs[i].st = L.add(sizeof(TaskState), 8);
     for (size_t i = 0; i < np; ++i) regs[i].I = L.add(8 * (int64_t)probs[i].kcap, 8);
@@ -982,6 +993,12 @@ static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, 
         regs[i].prevJ = L.add(8 * (int64_t)probs[i].kcap);
         regs[i].work = L.add(work_bytes(probs[i]));
         regs[i].strip = probs[i].need_strip ? L.add(strip_bytes(probs[i], prec64)) : -1;
+    }
+    int64_t packed = -1;
+    if (pack) {
+        const int64_t room = ctx->budget ? (int64_t)ctx->budget - (ctx->dev_in_use - ctx->dev.bytes) : INT64_MAX;
+        if (L.size + 16 * kk_all + 256 <= room) packed = L.add(16 * kk_all, 256);
+        else pack = false;
     }
     const int64_t total = L.size;
 
@@ -1012,7 +1029,16 @@ static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, 
         fill_task(htasks[i], probs[i], d, regs[i]);
     }
     *(uint64_t*)(h + off_err) = 0;
+    if (pack) {
+        int64_t* po = (int64_t*)(h + off_pack);
+        for (size_t i = 0; i < np; ++i) {
+            po[3 * i] = regs[i].st;
+            po[3 * i + 1] = regs[i].G;
+            po[3 * i + 2] = regs[i].U;
+        }
+    }
 
+    const double t_image = now_us();
     HIP_TRY(hipMemcpyAsync(d, h, (size_t)up_end, hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(launch_zero(d + z0, z1 - z0, ctx->stream));
     EngineArgs ea = engine_args(ctx, d, c, lp, phase_budget, (uint32_t*)(d + off_err),
@@ -1022,7 +1048,10 @@ static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, 
     if (rs != LRA_OK) return rs;
     if (ctx->timing) HIP_TRY(hipEventRecord(ctx->ev1, ctx->stream));
 
-    const int64_t rb1 = want_U ? u1 : want_G ? u0 : up_end;
+    if (pack)
+        HIP_TRY(launch_pack_factors(d, (const int64_t*)(d + off_pack), (int)np, (double*)(d + packed),
+                                    (double*)(d + packed) + kk_all, ctx->stream));
+    const int64_t rb1 = pack ? up_end : want_U ? u1 : want_G ? u0 : up_end;
     HIP_TRY(hipMemcpyAsync(h + rb0, d + rb0, (size_t)(rb1 - rb0), hipMemcpyDeviceToHost, ctx->stream));
     std::vector<uint64_t> trace_host;
     if (trace_cap) {
@@ -1030,7 +1059,9 @@ static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, 
         HIP_TRY(hipMemcpyAsync(trace_host.data(), d + off_trace, 8 * trace_host.size(), hipMemcpyDeviceToHost,
                                ctx->stream));
     }
+    const double t_enq = now_us();
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    const double t_wait = now_us();
     if (trace_cap) dump_trace(ctx, trace_host.data(), trace_cap);
     if (ctx->timing) {
         float ms = 0.f;
@@ -1042,11 +1073,39 @@ static lra_status run_batch(lra_ctx* ctx, std::vector<Prob>& probs, int prec64, 
         LRA_LOG(1, "device-side team barrier timed out");
         return LRA_EDEVICE;
     }
-    for (size_t i = 0; i < np; ++i) {
-        const ProbRegions& r = regs[i];
-        deliver(*(const TaskState*)(h + r.st), (const int64_t*)(h + r.I), (const int64_t*)(h + r.J),
-                want_G ? (const double*)(h + r.G) : nullptr, want_U ? (const double*)(h + r.U) : nullptr, res[i]);
+    if (pack) {
+        // the packed factors, at the offsets the pack kernel formed from the
+        // same final ranks, into the (unused) G and U staging regions
+        std::vector<int64_t> pb(np + 1, 0);
+        for (size_t i = 0; i < np; ++i) {
+            const int64_t k = ((const TaskState*)(h + regs[i].st))->k;
+            pb[i + 1] = pb[i] + k * k;
+        }
+        const int64_t hg = regs[0].G;
+        if (pb[np] > 0) {
+            if (want_G)
+                HIP_TRY(hipMemcpyAsync(h + hg, d + packed, 8 * (size_t)pb[np], hipMemcpyDeviceToHost, ctx->stream));
+            if (want_U)
+                HIP_TRY(hipMemcpyAsync(h + u0, d + packed + 8 * kk_all, 8 * (size_t)pb[np], hipMemcpyDeviceToHost,
+                                       ctx->stream));
+            HIP_TRY(hipStreamSynchronize(ctx->stream));
+        }
+        for (size_t i = 0; i < np; ++i) {
+            const ProbRegions& r = regs[i];
+            deliver(*(const TaskState*)(h + r.st), (const int64_t*)(h + r.I), (const int64_t*)(h + r.J),
+                    want_G ? (const double*)(h + hg) + pb[i] : nullptr, want_U ? (const double*)(h + u0) + pb[i] : nullptr,
+                    res[i]);
+        }
+    } else {
+        for (size_t i = 0; i < np; ++i) {
+            const ProbRegions& r = regs[i];
+            deliver(*(const TaskState*)(h + r.st), (const int64_t*)(h + r.I), (const int64_t*)(h + r.J),
+                    want_G ? (const double*)(h + r.G) : nullptr, want_U ? (const double*)(h + r.U) : nullptr, res[i]);
+        }
     }
+    LRA_LOG(2, "%zu problem(s): plan %.0f us, host image %.0f us, upload + launch %.0f us, wait %.0f us, "
+            "results %.0f us", np, t_plan1 - t_plan0, t_image - t_plan1, t_enq - t_image, t_wait - t_enq,
+            now_us() - t_wait);
     return LRA_OK;
 }
 
@@ -1308,20 +1367,40 @@ extern "C" lra_status lra_ca_cur_batched(lra_ctx* ctx, const lra_block* blocks, 
     else lra_default_options(&o);
     if (o.init_cols || o.sample_rows || o.sample_cols || o.init_rows) return LRA_EINVAL;
     const int prec64 = o.precision == LRA_PREC_FP64;
+    const double t0 = now_us();
     std::vector<Prob> probs(nblocks);
     std::vector<lra_result*> rp(nblocks);
-    for (int b = 0; b < nblocks; ++b) {
-        const lra_block& bl = blocks[b];
-        lra_status rs = make_prob(&bl.src, bl.m, bl.n, bl.k, bl.sweeps, bl.tol, &o, probs[b], b);
-        if (rs != LRA_OK) return rs;
-        // power-of-two team sizes keep the number of size classes small
-        probs[b].team = o.team_wgs > 0 ? std::min(o.team_wgs, NT)
-                                       : std::min(NT, pow2_ceil(auto_team(ctx, probs[b], prec64)));
-        probs[b].team_fixed = o.team_wgs > 0;
-        probs[b].C_out = results[b].C_out;
-        probs[b].R_out = results[b].R_out;
-        rp[b] = &results[b];
+    std::vector<lra_status> bst(nblocks, LRA_OK);
+    // each block's description (validation, seeded candidate and sample draws)
+    // is independent of the others: thousands of blocks are described on
+    // several host threads
+    const auto describe = [&](int b0, int b1) {
+        for (int b = b0; b < b1; ++b) {
+            const lra_block& bl = blocks[b];
+            bst[b] = make_prob(&bl.src, bl.m, bl.n, bl.k, bl.sweeps, bl.tol, &o, probs[b], b);
+            if (bst[b] != LRA_OK) continue;
+            // power-of-two team sizes keep the number of size classes small
+            probs[b].team = o.team_wgs > 0 ? std::min(o.team_wgs, NT)
+                                           : std::min(NT, pow2_ceil(auto_team(ctx, probs[b], prec64)));
+            probs[b].team_fixed = o.team_wgs > 0;
+            probs[b].C_out = results[b].C_out;
+            probs[b].R_out = results[b].R_out;
+            rp[b] = &results[b];
+        }
+    };
+    const int nthr = nblocks >= 256 ? std::max(1, std::min(8, (int)std::thread::hardware_concurrency())) : 1;
+    if (nthr > 1) {
+        std::vector<std::thread> pool;
+        const int per = (nblocks + nthr - 1) / nthr;
+        for (int t = 0; t < nthr; ++t)
+            if (t * per < nblocks) pool.emplace_back(describe, t * per, std::min(nblocks, (t + 1) * per));
+        for (auto& th : pool) th.join();
+    } else {
+        describe(0, nblocks);
     }
+    for (int b = 0; b < nblocks; ++b)
+        if (bst[b] != LRA_OK) return bst[b];
+    LRA_LOG(2, "%d block(s) described in %.0f us", nblocks, now_us() - t0);
     lra_status rs = run_batch(ctx, probs, prec64, 1 << 30, rp.data());
     if (rs != LRA_OK) return rs;
     lra_status worst = LRA_OK;

@@ -23,6 +23,10 @@ const void* engine_kernel_ptr(int, int)
 }
 hipError_t launch_engine(int, int, int, size_t, bool, const EngineArgs&, hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_zero(void*, int64_t, hipStream_t) { return hipErrorNoDevice; }
+hipError_t launch_pack_factors(const void*, const int64_t*, int, double*, double*, hipStream_t)
+{
+    return hipErrorNoDevice;
+}
 hipError_t launch_factors(const DevSource&, int64_t, int64_t, int, const int64_t*, const int64_t*, int, void*, void*,
                           hipStream_t)
 {
