@@ -214,6 +214,50 @@ def test_batched_repeatable(ctx):
         _same(runs[0][b], runs[2][b], f"block {b}, runs 0/2")
 
 
+def test_batched_packed_factors_partial_request(ctx):
+    """With 32 or more problems the k x k factors are packed on the device
+    before read-back.  A caller that asks for G and U of only some blocks
+    (null pointers elsewhere, through the C ABI) gets exactly the values of a
+    call that asks for all of them."""
+    import ctypes as C
+    lra = _lra()
+    _say("batched packed factors, partial request")
+    x, blocks = _multipole_case(1 << 14, 256)
+    xd = torch.from_numpy(x).cuda()
+    jobs = [(lra.invdist(xd[a0:a1], xd[b0:b1]), 8, 4, 1e-8) for (a0, a1, b0, b1) in blocks]
+    nb = len(jobs)
+    assert nb >= 32
+    _, full = ctx.ca_cur_batched(jobs, raise_on_error=False, k_max=48)
+    arr = lra._block_array(jobs)
+    o = lra.default_options(k_max=48)
+    res = (lra.ResultC * nb)()
+    I = np.zeros((nb, 48), dtype=np.int64)
+    J = np.zeros((nb, 48), dtype=np.int64)
+    G = np.full((nb, 48 * 48), -1.0)
+    U = np.full((nb, 48 * 48), -1.0)
+    for b in range(nb):
+        res[b].I = I[b].ctypes.data
+        res[b].J = J[b].ctypes.data
+        if b % 3 == 0:
+            res[b].G = G[b].ctypes.data
+        if b % 3 == 1:
+            res[b].U = U[b].ctypes.data
+    lra.lib().lra_ca_cur_batched(ctx._h, arr, nb, C.byref(o), res)
+    for b in range(nb):
+        k = res[b].k
+        assert (res[b].status, k) == (full[b].status, full[b].k), b
+        np.testing.assert_array_equal(I[b, :k], full[b].I)
+        np.testing.assert_array_equal(J[b, :k], full[b].J)
+        if b % 3 == 0:
+            np.testing.assert_array_equal(G[b, :k * k].reshape(k, k), full[b].G)
+        else:
+            assert (G[b] == -1.0).all()
+        if b % 3 == 1:
+            np.testing.assert_array_equal(U[b, :k * k].reshape(k, k), full[b].U)
+        else:
+            assert (U[b] == -1.0).all()
+
+
 def test_batched_mixed_precision_and_fixed_k(ctx):
     lra = _lra()
     _say("batched mixed / fixed k")
