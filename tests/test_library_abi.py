@@ -56,3 +56,30 @@ def test_noalloc_scratch_size_matches_header():
     m = re.search(r"#define LRA_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
     assert m and int(m.group(1)) << int(m.group(2)) == lra.NOALLOC_SCRATCH_BYTES
     assert "fixed scratch" in lra.status_str(lra.ESCRATCH)
+
+
+def test_block_records_filled_field_by_field():
+    """The batched call's block records are written through a numpy view of
+    the C array: each record must read back, through ctypes, exactly the
+    fields a per-element assignment would have written."""
+    class Src:
+        def __init__(self, i):
+            self.struct = lra.Source()
+            self.struct.kind = i % 4
+            self.struct.dtype = i % 2
+            self.struct.a = 4096 + 8 * i
+            self.struct.lda = 1000 + i
+            self.struct.col_major = i % 2
+            self.struct.pre_depth = i % 3
+            self.struct.x = 77 + i
+            self.struct.y = 99 + i
+            self.struct.pre_seed = (1 << 63) + i
+            self.m, self.n = 500 + i, 700 + 2 * i
+    blocks = [(Src(i), 8 + i % 5, 1 + i % 4, 1e-8 * (i + 1)) for i in range(37)]
+    arr = lra._block_array(blocks)
+    for i, (src, k, sweeps, tol) in enumerate(blocks):
+        r = arr[i]
+        for f, _ in lra.Source._fields_:
+            assert getattr(r.src, f) == getattr(src.struct, f), (i, f)
+        assert (r.m, r.n, r.k, r.sweeps, r.tol) == (src.m, src.n, k, sweeps, tol), i
+    assert len(lra._block_array([])) == 1
